@@ -1,0 +1,301 @@
+// Fused BLAS-1 updates and deterministic FP64 reductions of the CG solver.
+//
+// The paper ("Performance Measurement Method", Linear Solver Performance)
+// counts 50-100 flops per site for these operations, i.e. they are purely
+// bandwidth bound, and does every reduction in double precision.  Here each
+// thread owns one 4D site and walks its L5 slices (coalesced [s][group][cb]
+// accesses across the wavefront), the updates are fused so each vector is
+// read and written once, and every reduction accumulates in FP64 with a
+// fixed summation tree (DPP/shuffle within the wavefront, then LDS across
+// wavefronts, then one workgroup per right-hand side over the block
+// partials), so results are bitwise reproducible.
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace mdwf {
+
+// Sum over a 256-thread block in a fixed order; valid in thread 0.
+__device__ __forceinline__ double block_sum_256(double v) {
+  __shared__ double red[kBlasThreads / 64];
+  v += __shfl_xor(v, 32);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 8);
+  v += __shfl_xor(v, 4);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBlasThreads / 64; ++w) t += red[w];
+  return t;
+}
+
+template <int PX, int PS>
+__global__ __launch_bounds__(kBlasThreads) void k_cg_xr(BlasArgs A) {
+  using RX = typename PrecTraits<PX>::Real;
+  using RS = typename PrecTraits<PS>::Real;
+  const int slot = blockIdx.y;
+  const CGState& S = A.st[slot];
+  if (!S.active) return;
+  const int cb = blockIdx.x * kBlasThreads + threadIdx.x;
+  const FieldDesc f{A.g.Vh, A.g.L5};
+  const double alpha = S.alpha;
+  double loc = 0;
+  if (cb < A.g.Vh) {
+    char* x = A.a[slot];
+    const char* p = A.b[slot];
+    char* r = A.c[slot];
+    const char* q = A.d[slot];
+    for (int s = 0; s < A.g.L5; ++s) {
+      RS pv[24], qv[24], rv[24];
+      RX xv[24];
+      SpinorIO<PS>::load(p, f, cb, s, pv);
+      SpinorIO<PS>::load(q, f, cb, s, qv);
+      SpinorIO<PS>::load(r, f, cb, s, rv);
+      SpinorIO<PX>::load(x, f, cb, s, xv);
+#pragma unroll
+      for (int k = 0; k < 24; ++k) {
+        xv[k] += (RX)alpha * (RX)pv[k];
+        rv[k] -= (RS)alpha * qv[k];
+        loc += (double)rv[k] * (double)rv[k];
+      }
+      SpinorIO<PX>::store(x, f, cb, s, xv);
+      SpinorIO<PS>::store(r, f, cb, s, rv);
+    }
+  }
+  const double t = block_sum_256(loc);
+  if (threadIdx.x == 0) A.partials[(size_t)slot * A.nblk + blockIdx.x] = t;
+}
+
+template <int PS>
+__global__ __launch_bounds__(kBlasThreads) void k_cg_p(BlasArgs A) {
+  using RS = typename PrecTraits<PS>::Real;
+  const int slot = blockIdx.y;
+  const CGState& S = A.st[slot];
+  if (!S.active) return;
+  const int cb = blockIdx.x * kBlasThreads + threadIdx.x;
+  if (cb >= A.g.Vh) return;
+  const FieldDesc f{A.g.Vh, A.g.L5};
+  const RS beta = (RS)S.beta;
+  char* p = A.a[slot];
+  const char* r = A.b[slot];
+  for (int s = 0; s < A.g.L5; ++s) {
+    RS pv[24], rv[24];
+    SpinorIO<PS>::load(p, f, cb, s, pv);
+    SpinorIO<PS>::load(r, f, cb, s, rv);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) pv[k] = rv[k] + beta * pv[k];
+    SpinorIO<PS>::store(p, f, cb, s, pv);
+  }
+}
+
+template <int PI, int PO>
+__global__ __launch_bounds__(kBlasThreads) void k_axpby(BlasArgs A) {
+  using RI = typename PrecTraits<PI>::Real;
+  using RO = typename PrecTraits<PO>::Real;
+  using RC = typename PrecTraits<(PI == F64 || PO == F64) ? F64 : F32>::Real;
+  const int slot = blockIdx.y;
+  if (A.st != nullptr && !A.st[slot].active) return;
+  const int cb = blockIdx.x * kBlasThreads + threadIdx.x;
+  const FieldDesc f{A.g.Vh, A.g.L5};
+  double loc = 0;
+  if (cb < A.g.Vh) {
+    const char* in = A.a[slot];
+    char* out = A.b[slot];
+    const RC ca = (RC)A.ca, cbeta = (RC)A.cb;
+    for (int s = 0; s < A.g.L5; ++s) {
+      RI iv[24];
+      RO ov[24];
+      SpinorIO<PI>::load(in, f, cb, s, iv);
+      if (A.cb != 0.0) {
+        SpinorIO<PO>::load(out, f, cb, s, ov);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) ov[k] = (RO)(ca * (RC)iv[k] + cbeta * (RC)ov[k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) ov[k] = (RO)(ca * (RC)iv[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 24; ++k) loc += (double)ov[k] * (double)ov[k];
+      SpinorIO<PO>::store(out, f, cb, s, ov);
+    }
+  }
+  if (A.partials != nullptr) {
+    const double t = block_sum_256(loc);
+    if (threadIdx.x == 0) A.partials[(size_t)slot * A.nblk + blockIdx.x] = t;
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlasThreads) void k_norm_diff(BlasArgs A) {
+  using R = typename PrecTraits<P>::Real;
+  const int slot = blockIdx.y;
+  const int cb = blockIdx.x * kBlasThreads + threadIdx.x;
+  const FieldDesc f{A.g.Vh, A.g.L5};
+  double loc = 0;
+  if (cb < A.g.Vh) {
+    const char* a = A.a[slot];
+    const char* b = A.b != nullptr ? A.b[slot] : nullptr;
+    for (int s = 0; s < A.g.L5; ++s) {
+      R av[24], bv[24];
+      SpinorIO<P>::load(a, f, cb, s, av);
+      if (b != nullptr) {
+        SpinorIO<P>::load(b, f, cb, s, bv);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) av[k] -= bv[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 24; ++k) loc += (double)av[k] * (double)av[k];
+    }
+  }
+  const double t = block_sum_256(loc);
+  if (threadIdx.x == 0) A.partials[(size_t)slot * A.nblk + blockIdx.x] = t;
+}
+
+int blas_nblk(const Geom& g) { return (g.Vh + kBlasThreads - 1) / kBlasThreads; }
+
+static dim3 blas_grid(BlasArgs& A) {
+  A.nblk = blas_nblk(A.g);
+  return dim3(A.nblk, A.nslots);
+}
+
+hipError_t blas_cg_xr(BlasArgs A, int px, int ps, hipStream_t st) {
+  const dim3 grid = blas_grid(A);
+  const dim3 blk(kBlasThreads);
+  if (px == F64 && ps == F64) hipLaunchKernelGGL((k_cg_xr<F64, F64>), grid, blk, 0, st, A);
+  else if (px == F32 && ps == F32) hipLaunchKernelGGL((k_cg_xr<F32, F32>), grid, blk, 0, st, A);
+  else if (px == F32 && ps == F16) hipLaunchKernelGGL((k_cg_xr<F32, F16>), grid, blk, 0, st, A);
+  else if (px == F32 && ps == BF16) hipLaunchKernelGGL((k_cg_xr<F32, BF16>), grid, blk, 0, st, A);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t blas_cg_p(BlasArgs A, int ps, hipStream_t st) {
+  const dim3 grid = blas_grid(A);
+  const dim3 blk(kBlasThreads);
+  switch (ps) {
+    case F64: hipLaunchKernelGGL(k_cg_p<F64>, grid, blk, 0, st, A); break;
+    case F32: hipLaunchKernelGGL(k_cg_p<F32>, grid, blk, 0, st, A); break;
+    case F16: hipLaunchKernelGGL(k_cg_p<F16>, grid, blk, 0, st, A); break;
+    case BF16: hipLaunchKernelGGL(k_cg_p<BF16>, grid, blk, 0, st, A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int PI>
+static hipError_t axpby_out(BlasArgs A, int pout, dim3 grid, hipStream_t st) {
+  const dim3 blk(kBlasThreads);
+  switch (pout) {
+    case F64: hipLaunchKernelGGL((k_axpby<PI, F64>), grid, blk, 0, st, A); break;
+    case F32: hipLaunchKernelGGL((k_axpby<PI, F32>), grid, blk, 0, st, A); break;
+    case F16: hipLaunchKernelGGL((k_axpby<PI, F16>), grid, blk, 0, st, A); break;
+    case BF16: hipLaunchKernelGGL((k_axpby<PI, BF16>), grid, blk, 0, st, A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t blas_axpby(BlasArgs A, int pin, int pout, hipStream_t st) {
+  const dim3 grid = blas_grid(A);
+  switch (pin) {
+    case F64: return axpby_out<F64>(A, pout, grid, st);
+    case F32: return axpby_out<F32>(A, pout, grid, st);
+    case F16: return axpby_out<F16>(A, pout, grid, st);
+    case BF16: return axpby_out<BF16>(A, pout, grid, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t blas_norm_diff(BlasArgs A, int p, hipStream_t st) {
+  const dim3 grid = blas_grid(A);
+  const dim3 blk(kBlasThreads);
+  switch (p) {
+    case F64: hipLaunchKernelGGL(k_norm_diff<F64>, grid, blk, 0, st, A); break;
+    case F32: hipLaunchKernelGGL(k_norm_diff<F32>, grid, blk, 0, st, A); break;
+    case F16: hipLaunchKernelGGL(k_norm_diff<F16>, grid, blk, 0, st, A); break;
+    case BF16: hipLaunchKernelGGL(k_norm_diff<BF16>, grid, blk, 0, st, A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// scalar kernels: one 256-thread workgroup per right-hand side
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double slot_sum(const double* partials, int n, int slot) {
+  double v = 0;
+  for (int j = threadIdx.x; j < n; j += kBlasThreads) v += partials[(size_t)slot * n + j];
+  return block_sum_256(v);
+}
+
+__global__ __launch_bounds__(kBlasThreads) void k_reduce(const double* partials, int n, double* out) {
+  const double t = slot_sum(partials, n, blockIdx.x);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+__device__ __forceinline__ bool finite_d(double v) { return v == v && v - v == 0.0; }
+
+__global__ __launch_bounds__(kBlasThreads) void k_cg_alpha(CGState* S, const double* partials, int n) {
+  const int slot = blockIdx.x;
+  if (!S[slot].active) return;
+  const double pq = slot_sum(partials, n, slot);
+  if (threadIdx.x == 0) {
+    CGState& s = S[slot];
+    s.pq = pq;
+    if (!finite_d(pq)) {
+      s.flags |= CG_FLAG_NAN;
+      s.active = 0;
+    } else if (!(pq > 0.0)) {
+      s.flags |= CG_FLAG_BREAKDOWN;
+      s.active = 0;
+    } else {
+      s.alpha = s.rho / pq;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlasThreads) void k_cg_beta(CGState* S, const double* partials, int n) {
+  const int slot = blockIdx.x;
+  if (!S[slot].active) return;
+  const double rr = slot_sum(partials, n, slot);
+  if (threadIdx.x == 0) {
+    CGState& s = S[slot];
+    s.iters += 1;
+    s.rho_new = rr;
+    const double rn = sqrt(rr);
+    if (!finite_d(rr)) {
+      s.flags |= CG_FLAG_NAN;
+      s.active = 0;
+    } else if (rr <= s.tol2 || (s.delta > 0.0 && rn < s.delta * s.rmax)) {
+      // converged in the inner precision, or the residual fell by delta:
+      // the host recomputes the FP64 residual (reliable update)
+      s.flags |= CG_FLAG_UPDATE;
+      s.active = 0;
+    } else if (s.iters >= s.max_iter) {
+      s.flags |= CG_FLAG_MAXIT | CG_FLAG_UPDATE;
+      s.active = 0;
+    } else {
+      s.beta = rr / s.rho;
+      s.rho = rr;
+      if (rn > s.rmax) s.rmax = rn;
+    }
+  }
+}
+
+hipError_t scalar_reduce(const double* partials, int n, int nslots, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(nslots), dim3(kBlasThreads), 0, st, partials, n, out);
+  return hipGetLastError();
+}
+hipError_t scalar_cg_alpha(CGState* S, const double* partials, int n, int nslots, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(nslots), dim3(kBlasThreads), 0, st, S, partials, n);
+  return hipGetLastError();
+}
+hipError_t scalar_cg_beta(CGState* S, const double* partials, int n, int nslots, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_beta, dim3(nslots), dim3(kBlasThreads), 0, st, S, partials, n);
+  return hipGetLastError();
+}
+
+}  // namespace mdwf

@@ -1,0 +1,605 @@
+// libmdwf host core: contexts, validation, device memory, pointer tables,
+// profiling, the launch autotuner, gauge fields and sources.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "internal.h"
+
+using namespace mdwf;
+
+namespace mdwf {
+
+mdwf_status set_err(mdwf_ctx* c, mdwf_status s, const char* fmt, ...) {
+  if (c != nullptr) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+mdwf_status hip_err(mdwf_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return MDWF_OK;
+  if (e == hipErrorOutOfMemory) return set_err(c, MDWF_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+  return set_err(c, MDWF_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+mdwf_status check_action_msg(const mdwf_action* a, std::string& msg) {
+  if (a == nullptr) {
+    msg = "action is NULL";
+    return MDWF_EINVAL;
+  }
+  const char* nm[4] = {"Lx", "Ly", "Lz", "Lt"};
+  for (int m = 0; m < 4; ++m) {
+    if (a->L[m] < 2) {
+      msg = std::string(nm[m]) + " must be >= 2";
+      return MDWF_EINVAL;
+    }
+  }
+  if (a->L[0] % 2 != 0) {
+    msg = "Lx must be even (checkerboard indexing)";
+    return MDWF_EINVAL;
+  }
+  const double v4 = (double)a->L[0] * a->L[1] * a->L[2] * a->L[3];
+  if (v4 * (a->L5 > 0 ? a->L5 : 1) > 2.0e9) {
+    msg = "lattice too large (V4*L5 must stay below 2^31)";
+    return MDWF_EINVAL;
+  }
+  if (a->L5 < 1 || a->L5 > 32) {
+    msg = "L5 must be in [1, 32]";
+    return MDWF_EINVAL;
+  }
+  if (!std::isfinite(a->b5) || !std::isfinite(a->c5) || !std::isfinite(a->M5) || !std::isfinite(a->mq)) {
+    msg = "b5, c5, M5, mq must be finite";
+    return MDWF_EINVAL;
+  }
+  if (a->mq < 0) {
+    msg = "mq must be >= 0";
+    return MDWF_EINVAL;
+  }
+  const double alpha = a->b5 * (4.0 - a->M5) + 1.0;
+  if (alpha == 0.0) {
+    msg = "b5*(4-M5)+1 must be nonzero";
+    return MDWF_EINVAL;
+  }
+  const double kappa = (a->c5 * (4.0 - a->M5) - 1.0) / alpha;
+  if (1.0 + a->mq * std::pow(-kappa, a->L5) == 0.0) {
+    msg = "M5 is singular for these parameters";
+    return MDWF_EINVAL;
+  }
+  if (a->t_antiperiodic != 0 && a->t_antiperiodic != 1) {
+    msg = "t_antiperiodic must be 0 or 1";
+    return MDWF_EINVAL;
+  }
+  return MDWF_OK;
+}
+
+Geom make_geom(const mdwf_action* a) {
+  Geom g;
+  g.Lx = a->L[0];
+  g.Ly = a->L[1];
+  g.Lz = a->L[2];
+  g.Lt = a->L[3];
+  g.Lxh = a->L[0] / 2;
+  g.Vh = a->L[0] * a->L[1] * a->L[2] * a->L[3] / 2;
+  g.L5 = a->L5;
+  g.tap = a->t_antiperiodic;
+  return g;
+}
+
+Coef5 make_coef(const mdwf_action* a) {
+  Coef5 c;
+  c.b5 = a->b5;
+  c.c5 = a->c5;
+  c.mq = a->mq;
+  c.alpha = a->b5 * (4.0 - a->M5) + 1.0;
+  c.beta = a->c5 * (4.0 - a->M5) - 1.0;
+  c.kappa = c.beta / c.alpha;
+  c.inv_alpha = 1.0 / c.alpha;
+  c.inv_c = 1.0 / (1.0 + a->mq * std::pow(-c.kappa, a->L5));
+  return c;
+}
+
+mdwf_status ensure(mdwf_ctx* c, DevBuf& b, size_t n) {
+  if (b.n >= n) return MDWF_OK;
+  if (b.p != nullptr) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_err(c, e, "hipStreamSynchronize");
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.n = 0;
+  }
+  const size_t want = round_up(n, 4096);
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return hip_err(c, e, "hipMalloc (workspace)");
+  }
+  b.n = want;
+  return MDWF_OK;
+}
+
+void release(DevBuf& b) {
+  if (b.p != nullptr) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.n = 0;
+}
+
+static constexpr size_t kTableBytes = 1 << 20;
+
+// Small uploads (pointer tables, coefficients) go through a pinned mirror of
+// a device region, bump-allocated per top-level call.  A region offset is
+// rewritten only after the copies of the previous call have executed
+// (reset_tables waits for the event recorded after the latest upload).
+void reset_tables(mdwf_ctx* c) {
+  if (c->tables_ev != nullptr) (void)hipEventSynchronize(c->tables_ev);
+  c->tables_used = 0;
+}
+
+void* upload_bytes(mdwf_ctx* c, const void* data, size_t n) {
+  const size_t bytes = round_up(n > 0 ? n : 1, 256);
+  if (c->tables.p == nullptr) {
+    if (ensure(c, c->tables, kTableBytes) != MDWF_OK) return nullptr;
+    if (hipHostMalloc(&c->tables_host, kTableBytes, hipHostMallocDefault) != hipSuccess) {
+      c->tables_host = nullptr;
+      return nullptr;
+    }
+    if (hipEventCreateWithFlags(&c->tables_ev, hipEventDisableTiming) != hipSuccess) return nullptr;
+  }
+  if (bytes > kTableBytes) return nullptr;
+  if (c->tables_used + bytes > kTableBytes) {
+    // exhausted within one call: drain the stream, then start over
+    (void)hipStreamSynchronize(c->stream);
+    c->tables_used = 0;
+  }
+  char* dst = static_cast<char*>(c->tables.p) + c->tables_used;
+  char* src = static_cast<char*>(c->tables_host) + c->tables_used;
+  c->tables_used += bytes;
+  memcpy(src, data, n);
+  if (hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, c->stream) != hipSuccess) return nullptr;
+  (void)hipEventRecord(c->tables_ev, c->stream);
+  return dst;
+}
+
+char* const* upload_table(mdwf_ctx* c, const std::vector<const void*>& ptrs) {
+  return static_cast<char* const*>(upload_bytes(c, ptrs.data(), ptrs.size() * sizeof(void*)));
+}
+
+static hipEvent_t get_event(mdwf_ctx* c) {
+  if (!c->events.empty()) {
+    hipEvent_t e = c->events.back();
+    c->events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+void prof_begin(mdwf_ctx* c, hipEvent_t* e0) {
+  *e0 = nullptr;
+  if (!c->prof) return;
+  *e0 = get_event(c);
+  (void)hipEventRecord(*e0, c->stream);
+}
+
+void prof_end(mdwf_ctx* c, int cls, double bytes, hipEvent_t e0) {
+  if (!c->prof || e0 == nullptr) return;
+  hipEvent_t e1 = get_event(c);
+  (void)hipEventRecord(e1, c->stream);
+  c->pending.push_back(ProfRec{cls, bytes, e0, e1});
+  if (c->pending.size() > 4096) {
+    // fold finished records so the pool stays bounded
+    (void)hipEventSynchronize(e1);
+    for (auto& r : c->pending) {
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, r.e0, r.e1);
+      c->prof_launches[r.cls] += 1;
+      c->prof_ms[r.cls] += ms;
+      c->prof_bytes[r.cls] += r.bytes;
+      c->events.push_back(r.e0);
+      c->events.push_back(r.e1);
+    }
+    c->pending.clear();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused operator launch with the autotuner (the paper's "GPU Kernel
+// Autotuning": brute-force search of the launch space the first time a
+// kernel/problem key is met, kept in a std::map and looked up afterwards).
+// The tunable parameter is the number of sites per workgroup; all candidates
+// perform identical per-site arithmetic, and reductions use fixed 16-site
+// tiles, so tuning never changes results.  Launches whose output aliases an
+// input are not tuned (no backup/restore of destroyed data is needed then).
+// ---------------------------------------------------------------------------
+static std::string tune_key(const Geom& g, int prec, const Prog& p, int nslots) {
+  char buf[256];
+  snprintf(buf, sizeof(buf), "dslash5 p%d h%d d%d pr%d c%d.%d a%d r%d L%dx%dx%dx%d L5=%d n%d gfx950", prec,
+           (int)p.hop, (int)p.dag, (int)p.pro, p.c1, p.c2, p.aux, p.reduce, g.Lx, g.Ly, g.Lz, g.Lt, g.L5, nslots);
+  return buf;
+}
+
+static void candidates(const Geom& g, int prec, const DslashArgs& A, std::vector<int>& out, int& dflt) {
+  out.clear();
+  dflt = -1;
+  for (int lg = 4; lg <= 7; ++lg) {
+    const int CB = 1 << lg;
+    if (CB * g.L5 > dslash_max_threads(prec)) break;
+    if (CB > 2 * g.Vh && lg > 4) break;
+    const size_t lds = dslash_lds_bytes(A, prec, lg);
+    if (lds > 160 * 1024) break;
+    out.push_back(lg);
+    if (lds <= 64 * 1024 && CB <= 64) dflt = lg;
+  }
+  if (dflt < 0 && !out.empty()) dflt = out.front();
+}
+
+static double prog_bytes(const Geom& g, int prec, const Prog& p, int nslots) {
+  const double ne = (double)g.Vh * g.L5;
+  const double sb = spinor_site_bytes(prec);
+  double per = 2.0 + (p.aux != AUX_NONE ? 1.0 : 0.0);
+  double b = nslots * ne * sb * per;
+  if (p.hop) b += 8.0 * g.Vh * 12.0 * link_real_bytes(prec);
+  return b;
+}
+
+hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int prec, const Prog& pr,
+                    char* const* in, char* const* aux, char* const* out, const Coef5* coef_d, int nslots,
+                    const int* active, int active_stride, double* partials, int ntiles, int cls, bool tunable) {
+  DslashArgs A{};
+  A.g = geom;
+  A.out_par = pr.out_par;
+  A.gauge = gf != nullptr ? static_cast<const char*>(gf->data[prec]) : nullptr;
+  A.in = in;
+  A.aux = aux;
+  A.out = out;
+  A.coef = coef_d;
+  A.active = active;
+  A.active_stride = active_stride;
+  A.partials = partials;
+  A.ntiles = ntiles;
+  A.nslots = nslots;
+  A.c1 = pr.c1;
+  A.c2 = pr.c2;
+  A.aux_mode = pr.aux;
+  A.reduce = pr.reduce;
+  A.coef_y = pr.coef;
+  std::vector<int> cand;
+  int dflt = 4;
+  candidates(geom, prec, A, cand, dflt);
+  if (cand.empty()) return hipErrorInvalidValue;
+  int lg = dflt;
+  const std::string key = tune_key(geom, prec, pr, nslots);
+  auto it = c->tune.find(key);
+  if (it != c->tune.end()) {
+    lg = it->second;
+  } else if (c->tune_mode == 1 && tunable && cand.size() > 1) {
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    float best = 1e30f;
+    int best_lg = dflt;
+    for (int cl : cand) {
+      hipError_t e = dslash_launch(A, prec, pr.hop, pr.dag, pr.pro, cl, c->stream);  // warm-up
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        continue;
+      }
+      (void)hipEventRecord(e0, c->stream);
+      for (int r = 0; r < 3; ++r) (void)dslash_launch(A, prec, pr.hop, pr.dag, pr.pro, cl, c->stream);
+      (void)hipEventRecord(e1, c->stream);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        best_lg = cl;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    lg = best_lg;
+    c->tune[key] = lg;
+    c->tune_ms[key] = best / 3.0f;
+  }
+  hipEvent_t ev;
+  prof_begin(c, &ev);
+  hipError_t e = dslash_launch(A, prec, pr.hop, pr.dag, pr.pro, lg, c->stream);
+  prof_end(c, cls, prog_bytes(geom, prec, pr, nslots), ev);
+  return e;
+}
+
+}  // namespace mdwf
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int32_t mdwf_abi_version(void) { return MDWF_ABI_VERSION; }
+
+mdwf_status mdwf_check_action(const mdwf_action* act, char* msg, size_t msg_len) {
+  std::string m;
+  mdwf_status s = check_action_msg(act, m);
+  if (msg != nullptr && msg_len > 0) {
+    snprintf(msg, msg_len, "%s", m.c_str());
+  }
+  return s;
+}
+
+mdwf_status mdwf_create(int32_t device, void* stream, mdwf_ctx** out) {
+  if (out == nullptr) return MDWF_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return MDWF_EHIP;
+  if (device < 0 || device >= n) return MDWF_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return MDWF_EHIP;
+  mdwf_ctx* c = new (std::nothrow) mdwf_ctx();
+  if (c == nullptr) return MDWF_ENOMEM;
+  c->device = device;
+  if (stream != nullptr) {
+    c->stream = static_cast<hipStream_t>(stream);
+    c->own_stream = false;
+  } else {
+    // a blocking stream: it stays ordered with the legacy default stream,
+    // where torch enqueues its work unless told otherwise
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamDefault) != hipSuccess) {
+      delete c;
+      return MDWF_EHIP;
+    }
+    c->own_stream = true;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->red_host), 4096 * sizeof(double), hipHostMallocDefault) !=
+      hipSuccess) {
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return MDWF_ENOMEM;
+  }
+  c->red_host_n = 4096;
+  const char* tm = getenv("MDWF_TUNE");
+  if (tm != nullptr && tm[0] == '1') c->tune_mode = 1;
+  const char* tc = getenv("MDWF_TUNE_CACHE");
+  if (tc != nullptr && tc[0] != 0) (void)mdwf_tune_load(c, tc);
+  *out = c;
+  return MDWF_OK;
+}
+
+mdwf_status mdwf_destroy(mdwf_ctx* c) {
+  if (c == nullptr) return MDWF_EINVAL;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& r : c->pending) {
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  for (auto e : c->events) (void)hipEventDestroy(e);
+  release(c->tables);
+  if (c->tables_host != nullptr) (void)hipHostFree(c->tables_host);
+  if (c->tables_ev != nullptr) (void)hipEventDestroy(c->tables_ev);
+  release(c->partials_d);
+  release(c->partials_b);
+  release(c->states);
+  release(c->coefs);
+  release(c->red_out);
+  for (auto& b : c->tmp64) release(b);
+  release(c->dws);
+  if (c->red_host != nullptr) (void)hipHostFree(c->red_host);
+  if (c->st_host != nullptr) (void)hipHostFree(c->st_host);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  const char* tc = getenv("MDWF_TUNE_CACHE");
+  if (tc != nullptr && tc[0] != 0 && !c->tune.empty()) (void)mdwf_tune_save(c, tc);
+  delete c;
+  return MDWF_OK;
+}
+
+const char* mdwf_last_error(const mdwf_ctx* c) { return c == nullptr ? "null context" : c->err.c_str(); }
+
+void* mdwf_stream(const mdwf_ctx* c) { return c == nullptr ? nullptr : static_cast<void*>(c->stream); }
+
+mdwf_status mdwf_gauge_load(mdwf_ctx* c, const int32_t L[4], const void* links, int32_t where, uint32_t prec_mask,
+                            mdwf_gauge** out) {
+  if (c == nullptr) return MDWF_EINVAL;
+  if (out == nullptr || L == nullptr || links == nullptr)
+    return set_err(c, MDWF_EINVAL, "mdwf_gauge_load: NULL argument");
+  *out = nullptr;
+  if (where != MDWF_HOST && where != MDWF_DEVICE) return set_err(c, MDWF_EINVAL, "mdwf_gauge_load: bad `where`");
+  mdwf_action a{};
+  for (int m = 0; m < 4; ++m) a.L[m] = L[m];
+  a.L5 = 1;
+  a.b5 = 1;
+  a.c5 = 0;
+  a.M5 = 1;
+  a.mq = 0;
+  std::string msg;
+  if (check_action_msg(&a, msg) != MDWF_OK) return set_err(c, MDWF_EINVAL, "mdwf_gauge_load: %s", msg.c_str());
+  if (prec_mask & ~0xfu) return set_err(c, MDWF_EINVAL, "mdwf_gauge_load: prec_mask has unknown bits");
+  prec_mask |= 1u << MDWF_F64;
+  (void)hipSetDevice(c->device);
+  const Geom g = make_geom(&a);
+  const size_t user_bytes = (size_t)g.Vh * 2 * 4 * 18 * sizeof(double);
+  mdwf_gauge* gf = new (std::nothrow) mdwf_gauge();
+  if (gf == nullptr) return set_err(c, MDWF_ENOMEM, "host allocation");
+  gf->ctx = c;
+  for (int m = 0; m < 4; ++m) gf->L[m] = L[m];
+  gf->Vh = g.Vh;
+  const double* dev_links = static_cast<const double*>(links);
+  void* staging = nullptr;
+  hipError_t e;
+  if (where == MDWF_HOST) {
+    e = hipMalloc(&staging, user_bytes);
+    if (e != hipSuccess) {
+      delete gf;
+      return hip_err(c, e, "hipMalloc (gauge staging)");
+    }
+    e = hipMemcpyAsync(staging, links, user_bytes, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) {
+      (void)hipFree(staging);
+      delete gf;
+      return hip_err(c, e, "hipMemcpyAsync (gauge)");
+    }
+    dev_links = static_cast<const double*>(staging);
+  }
+  mdwf_status st = MDWF_OK;
+  for (int p = 0; p < 4 && st == MDWF_OK; ++p) {
+    if (!(prec_mask & (1u << p))) continue;
+    const size_t nb = gauge_field_bytes(p, g.Vh);
+    e = hipMalloc(&gf->data[p], nb);
+    if (e != hipSuccess) {
+      gf->data[p] = nullptr;
+      st = hip_err(c, e, "hipMalloc (gauge)");
+      break;
+    }
+    gf->bytes += nb;
+    e = layout_gauge(g, dev_links, static_cast<char*>(gf->data[p]), p, c->stream);
+    if (e != hipSuccess) st = hip_err(c, e, "gauge layout kernel");
+  }
+  e = hipStreamSynchronize(c->stream);
+  if (st == MDWF_OK && e != hipSuccess) st = hip_err(c, e, "gauge load");
+  if (staging != nullptr) (void)hipFree(staging);
+  if (st != MDWF_OK) {
+    for (int p = 0; p < 4; ++p)
+      if (gf->data[p] != nullptr) (void)hipFree(gf->data[p]);
+    delete gf;
+    return st;
+  }
+  *out = gf;
+  return MDWF_OK;
+}
+
+mdwf_status mdwf_gauge_free(mdwf_gauge* g) {
+  if (g == nullptr) return MDWF_EINVAL;
+  if (g->ctx != nullptr) {
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);
+  }
+  for (int p = 0; p < 4; ++p)
+    if (g->data[p] != nullptr) (void)hipFree(g->data[p]);
+  delete g;
+  return MDWF_OK;
+}
+
+size_t mdwf_gauge_bytes(const mdwf_gauge* g) { return g == nullptr ? 0 : g->bytes; }
+
+mdwf_status mdwf_source_point(mdwf_ctx* c, const mdwf_action* act, const int32_t x0[4], int32_t spin, int32_t colour,
+                              void* eta) {
+  if (c == nullptr) return MDWF_EINVAL;
+  std::string msg;
+  if (check_action_msg(act, msg) != MDWF_OK) return set_err(c, MDWF_EINVAL, "mdwf_source_point: %s", msg.c_str());
+  if (x0 == nullptr || eta == nullptr) return set_err(c, MDWF_EINVAL, "mdwf_source_point: NULL argument");
+  for (int m = 0; m < 4; ++m)
+    if (x0[m] < 0 || x0[m] >= act->L[m]) return set_err(c, MDWF_EINVAL, "mdwf_source_point: x0 outside the lattice");
+  if (spin < 0 || spin > 3 || colour < 0 || colour > 2)
+    return set_err(c, MDWF_EINVAL, "mdwf_source_point: spin in [0,4), colour in [0,3)");
+  (void)hipSetDevice(c->device);
+  const Geom g = make_geom(act);
+  int x[4] = {x0[0], x0[1], x0[2], x0[3]};
+  hipEvent_t ev;
+  prof_begin(c, &ev);
+  hipError_t e = source_point(g, static_cast<double*>(eta), x, spin, colour, c->stream);
+  prof_end(c, MDWF_PROF_OTHER, (double)g.Vh * 2 * g.L5 * 192, ev);
+  return hip_err(c, e, "source_point");
+}
+
+mdwf_status mdwf_source_z2(mdwf_ctx* c, const mdwf_action* act, uint64_t seed, int32_t rhs_index, void* eta) {
+  if (c == nullptr) return MDWF_EINVAL;
+  std::string msg;
+  if (check_action_msg(act, msg) != MDWF_OK) return set_err(c, MDWF_EINVAL, "mdwf_source_z2: %s", msg.c_str());
+  if (eta == nullptr || rhs_index < 0) return set_err(c, MDWF_EINVAL, "mdwf_source_z2: bad argument");
+  (void)hipSetDevice(c->device);
+  const Geom g = make_geom(act);
+  hipEvent_t ev;
+  prof_begin(c, &ev);
+  hipError_t e = source_z2(g, static_cast<double*>(eta), seed, rhs_index, c->stream);
+  prof_end(c, MDWF_PROF_OTHER, (double)g.Vh * 2 * g.L5 * 192, ev);
+  return hip_err(c, e, "source_z2");
+}
+
+mdwf_status mdwf_profile_enable(mdwf_ctx* c, int32_t on) {
+  if (c == nullptr) return MDWF_EINVAL;
+  c->prof = on != 0;
+  return MDWF_OK;
+}
+
+static void fold_profile(mdwf_ctx* c) {
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& r : c->pending) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, r.e0, r.e1);
+    c->prof_launches[r.cls] += 1;
+    c->prof_ms[r.cls] += ms;
+    c->prof_bytes[r.cls] += r.bytes;
+    c->events.push_back(r.e0);
+    c->events.push_back(r.e1);
+  }
+  c->pending.clear();
+}
+
+mdwf_status mdwf_profile_reset(mdwf_ctx* c) {
+  if (c == nullptr) return MDWF_EINVAL;
+  fold_profile(c);
+  for (int k = 0; k < MDWF_PROF_NCLASS; ++k) {
+    c->prof_launches[k] = 0;
+    c->prof_ms[k] = 0;
+    c->prof_bytes[k] = 0;
+  }
+  return MDWF_OK;
+}
+
+mdwf_status mdwf_profile_read(mdwf_ctx* c, int32_t cls, int64_t* launches, double* ms, double* bytes) {
+  if (c == nullptr) return MDWF_EINVAL;
+  if (cls < 0 || cls >= MDWF_PROF_NCLASS) return set_err(c, MDWF_EINVAL, "profile class out of range");
+  fold_profile(c);
+  if (launches) *launches = c->prof_launches[cls];
+  if (ms) *ms = c->prof_ms[cls];
+  if (bytes) *bytes = c->prof_bytes[cls];
+  return MDWF_OK;
+}
+
+mdwf_status mdwf_tune_mode(mdwf_ctx* c, int32_t mode) {
+  if (c == nullptr) return MDWF_EINVAL;
+  if (mode != 0 && mode != 1) return set_err(c, MDWF_EINVAL, "tune mode must be 0 or 1");
+  c->tune_mode = mode;
+  return MDWF_OK;
+}
+
+mdwf_status mdwf_tune_save(const mdwf_ctx* c, const char* path) {
+  if (c == nullptr || path == nullptr) return MDWF_EINVAL;
+  std::ofstream f(path);
+  if (!f) return MDWF_EINVAL;
+  for (auto& kv : c->tune) {
+    auto m = c->tune_ms.find(kv.first);
+    f << kv.first << " | " << kv.second << " " << (m != c->tune_ms.end() ? m->second : 0.0f) << "\n";
+  }
+  return MDWF_OK;
+}
+
+mdwf_status mdwf_tune_load(mdwf_ctx* c, const char* path) {
+  if (c == nullptr || path == nullptr) return MDWF_EINVAL;
+  std::ifstream f(path);
+  if (!f) return set_err(c, MDWF_EINVAL, "cannot open tune table %s", path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t bar = line.find(" | ");
+    if (bar == std::string::npos) continue;
+    std::istringstream rest(line.substr(bar + 3));
+    int lg = -1;
+    float ms = 0;
+    rest >> lg >> ms;
+    if (lg >= 4 && lg <= 7) {
+      c->tune[line.substr(0, bar)] = lg;
+      c->tune_ms[line.substr(0, bar)] = ms;
+    }
+  }
+  return MDWF_OK;
+}
+
+int32_t mdwf_tune_entries(const mdwf_ctx* c) { return c == nullptr ? 0 : (int32_t)c->tune.size(); }
+
+}  // extern "C"

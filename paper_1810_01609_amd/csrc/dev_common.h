@@ -1,0 +1,367 @@
+// Device-side building blocks shared by the HIP kernels of libmdwf:
+// precision traits, the internal field layouts, site geometry and complex
+// arithmetic.  gfx950 only.
+//
+// Internal layouts (one parity, "half-field"; cb = lexicographic 4D index
+// of the site divided by 2, which enumerates one parity when Lx is even):
+//   spinor F64 : double2 [s][12 groups][cb]      group g = complex comp g
+//   spinor F32 : float4  [s][6 groups][cb]       group g = comps 2g, 2g+1
+//   spinor F16/BF16 : 16-byte groups of 8 halves [s][3][cb] (comps 4g..4g+3),
+//              then (256-byte aligned) float scale [s][cb]: value = half*scale
+//   gauge  : 12 reals (rows 0,1) per link, [parity][mu][group][cb]
+//            F64 6 x double2, F32 3 x float4, F16/BF16 3 x 4 halves (8 bytes)
+// Complex component index comp = spin*3 + colour, reals interleaved re,im.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace mdwf {
+
+enum Prec : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3 };
+
+template <int P> struct PrecTraits;
+template <> struct PrecTraits<F64> { using Real = double; };
+template <> struct PrecTraits<F32> { using Real = float; };
+template <> struct PrecTraits<F16> { using Real = float; };
+template <> struct PrecTraits<BF16> { using Real = float; };
+
+__host__ __device__ __forceinline__ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Byte offset of the per-site scale array inside a 16-bit spinor field.
+__host__ __device__ __forceinline__ size_t half_scale_offset(int L5, int Vh) {
+  return round_up((size_t)L5 * (size_t)Vh * 48u, 256u);
+}
+
+// Bytes of one spinor half-field of precision p.
+__host__ __device__ __forceinline__ size_t spinor_field_bytes(int p, int L5, int Vh) {
+  const size_t n = (size_t)L5 * (size_t)Vh;
+  switch (p) {
+    case F64: return n * 192u;
+    case F32: return n * 96u;
+    default: return half_scale_offset(L5, Vh) + n * 4u;
+  }
+}
+
+// Bytes one spinor site costs in HBM traffic (data + scale).
+__host__ __device__ __forceinline__ int spinor_site_bytes(int p) { return p == F64 ? 192 : p == F32 ? 96 : 52; }
+__host__ __device__ __forceinline__ int link_real_bytes(int p) { return p == F64 ? 8 : p == F32 ? 4 : 2; }
+
+// Bytes of one gauge field (both parities, 4 directions, 12 reals per link).
+__host__ __device__ __forceinline__ size_t gauge_field_bytes(int p, int Vh) {
+  return (size_t)2 * 4 * 12 * (size_t)Vh * link_real_bytes(p);
+}
+
+struct Geom {
+  int Lx, Ly, Lz, Lt;  // lattice extents (Lx even)
+  int Lxh;             // Lx / 2
+  int Vh;              // sites per parity
+  int L5;
+  int tap;             // 1: antiperiodic in t
+};
+
+// 4D coordinates of the site with checkerboard index cb and parity par.
+__device__ __forceinline__ void site_coords(const Geom& g, int par, int cb, int& x, int& y, int& z, int& t) {
+  const int xh = cb % g.Lxh;
+  int r = cb / g.Lxh;
+  y = r % g.Ly;
+  r /= g.Ly;
+  z = r % g.Lz;
+  t = r / g.Lz;
+  x = 2 * xh + ((par + y + z + t) & 1);
+}
+
+__device__ __forceinline__ int cb_index(const Geom& g, int x, int y, int z, int t) {
+  return (((t * g.Lz + z) * g.Ly + y) * g.Lx + x) >> 1;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin; remap so that each XCD
+// processes one contiguous range of logical blocks (neighbouring sites and
+// all right-hand sides of a site stay in one XCD's L2).
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  if (nb & 7) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// Global-memory accesses.  Field pointers come out of device pointer tables,
+// so the compiler cannot tell they are global; without the explicit address
+// space it emits generic (flat) loads that wait on both memory counters.
+// ---------------------------------------------------------------------------
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MDWF_GLOBAL __attribute__((address_space(1)))
+#else
+#define MDWF_GLOBAL
+#endif
+template <class V> __device__ __forceinline__ V ldg(const void* p) { return *(const MDWF_GLOBAL V*)(p); }
+template <class V> __device__ __forceinline__ void stg(void* p, V v) { *(MDWF_GLOBAL V*)(p) = v; }
+
+// ---------------------------------------------------------------------------
+// complex arithmetic
+// ---------------------------------------------------------------------------
+template <class R> struct Cplx { R re, im; };
+
+template <class R> __device__ __forceinline__ Cplx<R> cmul(Cplx<R> a, Cplx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <class R> __device__ __forceinline__ Cplx<R> cjmul(Cplx<R> a, Cplx<R> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+
+// ---------------------------------------------------------------------------
+// 16-bit conversions (IEEE bit manipulation; round to nearest even)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float bf16_to_float(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
+__device__ __forceinline__ uint32_t float_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ __forceinline__ float f16_to_float(uint32_t bits16) {
+  return __half2float(__ushort_as_half((unsigned short)bits16));
+}
+__device__ __forceinline__ uint32_t float_to_f16(float f) {
+  return (uint32_t)__half_as_ushort(__float2half_rn(f));
+}
+
+template <int P> __device__ __forceinline__ float h_to_f(uint32_t b) {
+  if constexpr (P == F16) return f16_to_float(b);
+  else return bf16_to_float(b);
+}
+template <int P> __device__ __forceinline__ uint32_t f_to_h(float f) {
+  if constexpr (P == F16) return float_to_f16(f);
+  else return float_to_bf16(f);
+}
+template <int P> __device__ __forceinline__ void unpack2(uint32_t w, float& a, float& b) {
+  a = h_to_f<P>(w & 0xffffu);
+  b = h_to_f<P>(w >> 16);
+}
+template <int P> __device__ __forceinline__ uint32_t pack2(float a, float b) {
+  return f_to_h<P>(a) | (f_to_h<P>(b) << 16);
+}
+
+// ---------------------------------------------------------------------------
+// Spinor storage.  A site is 24 reals v[k], k = 2*comp + (0 re | 1 im).
+// ---------------------------------------------------------------------------
+struct FieldDesc {
+  int Vh, L5;
+};
+
+template <int P> struct SpinorIO;
+
+template <> struct SpinorIO<F64> {
+  using R = double;
+  static __device__ __forceinline__ void load(const char* base, const FieldDesc& f, int cb, int s, R v[24]) {
+    const double2* p = reinterpret_cast<const double2*>(base) + (size_t)s * 12 * f.Vh + cb;
+#pragma unroll
+    for (int g = 0; g < 12; ++g) {
+      const v2d d = ldg<v2d>(p + (size_t)g * f.Vh);
+      v[2 * g] = d.x;
+      v[2 * g + 1] = d.y;
+    }
+  }
+  // h = 0: comps 0..5 (spins 0,1); h = 1: comps 6..11 (spins 2,3)
+  static __device__ __forceinline__ void load_half(const char* base, const FieldDesc& f, int cb, int s, int h, R v[12]) {
+    const double2* p = reinterpret_cast<const double2*>(base) + ((size_t)s * 12 + 6 * h) * f.Vh + cb;
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+      const v2d d = ldg<v2d>(p + (size_t)g * f.Vh);
+      v[2 * g] = d.x;
+      v[2 * g + 1] = d.y;
+    }
+  }
+  static __device__ __forceinline__ void store(char* base, const FieldDesc& f, int cb, int s, const R v[24]) {
+    double2* p = reinterpret_cast<double2*>(base) + (size_t)s * 12 * f.Vh + cb;
+#pragma unroll
+    for (int g = 0; g < 12; ++g) stg<v2d>(p + (size_t)g * f.Vh, v2d{v[2 * g], v[2 * g + 1]});
+  }
+};
+
+template <> struct SpinorIO<F32> {
+  using R = float;
+  static __device__ __forceinline__ void load(const char* base, const FieldDesc& f, int cb, int s, R v[24]) {
+    const float4* p = reinterpret_cast<const float4*>(base) + (size_t)s * 6 * f.Vh + cb;
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+      const v4f d = ldg<v4f>(p + (size_t)g * f.Vh);
+      v[4 * g] = d.x;
+      v[4 * g + 1] = d.y;
+      v[4 * g + 2] = d.z;
+      v[4 * g + 3] = d.w;
+    }
+  }
+  static __device__ __forceinline__ void load_half(const char* base, const FieldDesc& f, int cb, int s, int h, R v[12]) {
+    const float4* p = reinterpret_cast<const float4*>(base) + ((size_t)s * 6 + 3 * h) * f.Vh + cb;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      const v4f d = ldg<v4f>(p + (size_t)g * f.Vh);
+      v[4 * g] = d.x;
+      v[4 * g + 1] = d.y;
+      v[4 * g + 2] = d.z;
+      v[4 * g + 3] = d.w;
+    }
+  }
+  static __device__ __forceinline__ void store(char* base, const FieldDesc& f, int cb, int s, const R v[24]) {
+    float4* p = reinterpret_cast<float4*>(base) + (size_t)s * 6 * f.Vh + cb;
+#pragma unroll
+    for (int g = 0; g < 6; ++g) stg<v4f>(p + (size_t)g * f.Vh, v4f{v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]});
+  }
+};
+
+template <int P> struct SpinorIO16 {
+  using R = float;
+  static __device__ __forceinline__ float scale(const char* base, const FieldDesc& f, int cb, int s) {
+    return ldg<float>(reinterpret_cast<const float*>(base + half_scale_offset(f.L5, f.Vh)) + (size_t)s * f.Vh + cb);
+  }
+  static __device__ __forceinline__ void group(const char* base, const FieldDesc& f, int cb, int s, int g, float sc, R* v) {
+    const v4u q = ldg<v4u>(reinterpret_cast<const uint4*>(base) + ((size_t)s * 3 + g) * f.Vh + cb);
+    unpack2<P>(q.x, v[0], v[1]);
+    unpack2<P>(q.y, v[2], v[3]);
+    unpack2<P>(q.z, v[4], v[5]);
+    unpack2<P>(q.w, v[6], v[7]);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] *= sc;
+  }
+  static __device__ __forceinline__ void load(const char* base, const FieldDesc& f, int cb, int s, R v[24]) {
+    const float sc = scale(base, f, cb, s);
+#pragma unroll
+    for (int g = 0; g < 3; ++g) group(base, f, cb, s, g, sc, v + 8 * g);
+  }
+  static __device__ __forceinline__ void load_half(const char* base, const FieldDesc& f, int cb, int s, int h, R v[12]) {
+    const float sc = scale(base, f, cb, s);
+    R t[16];
+    // reals 0..11 live in groups 0 and 1 (first half), reals 12..23 in group 1 (second half) and 2
+    group(base, f, cb, s, h, sc, t);
+    group(base, f, cb, s, h + 1, sc, t + 8);
+    if (h == 0) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v[k] = t[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v[k] = t[k + 4];
+    }
+  }
+  static __device__ __forceinline__ void store(char* base, const FieldDesc& f, int cb, int s, const R v[24]) {
+    float m = 0.f;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf(v[k]));
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
+    uint4* p = reinterpret_cast<uint4*>(base) + (size_t)s * 3 * f.Vh + cb;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      const R* w = v + 8 * g;
+      const v4u q{pack2<P>(w[0] * inv, w[1] * inv), pack2<P>(w[2] * inv, w[3] * inv),
+                  pack2<P>(w[4] * inv, w[5] * inv), pack2<P>(w[6] * inv, w[7] * inv)};
+      stg<v4u>(p + (size_t)g * f.Vh, q);
+    }
+    stg<float>(reinterpret_cast<float*>(base + half_scale_offset(f.L5, f.Vh)) + (size_t)s * f.Vh + cb, m);
+  }
+};
+template <> struct SpinorIO<F16> : SpinorIO16<F16> {};
+template <> struct SpinorIO<BF16> : SpinorIO16<BF16> {};
+
+// ---------------------------------------------------------------------------
+// Gauge links: 12 stored reals, row 2 = conj(row0 x row1).
+// ---------------------------------------------------------------------------
+template <class R> __device__ __forceinline__ void reconstruct_row2(Cplx<R> U[3][3]) {
+  // u2j = conj(u0k u1l - u0l u1k), (j,k,l) cyclic
+  Cplx<R> a, b;
+  a = cmul(U[0][1], U[1][2]); b = cmul(U[0][2], U[1][1]);
+  U[2][0] = {a.re - b.re, -(a.im - b.im)};
+  a = cmul(U[0][2], U[1][0]); b = cmul(U[0][0], U[1][2]);
+  U[2][1] = {a.re - b.re, -(a.im - b.im)};
+  a = cmul(U[0][0], U[1][1]); b = cmul(U[0][1], U[1][0]);
+  U[2][2] = {a.re - b.re, -(a.im - b.im)};
+}
+
+template <int P> struct LinkIO;
+
+template <> struct LinkIO<F64> {
+  using R = double;
+  static __device__ __forceinline__ void load(const char* gbase, int Vh, int par, int mu, int cb, Cplx<R> U[3][3]) {
+    const double2* p = reinterpret_cast<const double2*>(gbase) + (size_t)((par * 4 + mu) * 6) * Vh + cb;
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+      const v2d d = ldg<v2d>(p + (size_t)g * Vh);
+      U[g / 3][g % 3] = {d.x, d.y};
+    }
+    reconstruct_row2(U);
+  }
+};
+
+template <> struct LinkIO<F32> {
+  using R = float;
+  static __device__ __forceinline__ void load(const char* gbase, int Vh, int par, int mu, int cb, Cplx<R> U[3][3]) {
+    const float4* p = reinterpret_cast<const float4*>(gbase) + (size_t)((par * 4 + mu) * 3) * Vh + cb;
+    float r[12];
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      const v4f d = ldg<v4f>(p + (size_t)g * Vh);
+      r[4 * g] = d.x; r[4 * g + 1] = d.y; r[4 * g + 2] = d.z; r[4 * g + 3] = d.w;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) U[k / 3][k % 3] = {r[2 * k], r[2 * k + 1]};
+    reconstruct_row2(U);
+  }
+};
+
+template <int P> struct LinkIO16 {
+  using R = float;
+  static __device__ __forceinline__ void load(const char* gbase, int Vh, int par, int mu, int cb, Cplx<R> U[3][3]) {
+    const uint2* p = reinterpret_cast<const uint2*>(gbase) + (size_t)((par * 4 + mu) * 3) * Vh + cb;
+    float r[12];
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      const v2u d = ldg<v2u>(p + (size_t)g * Vh);
+      unpack2<P>(d.x, r[4 * g], r[4 * g + 1]);
+      unpack2<P>(d.y, r[4 * g + 2], r[4 * g + 3]);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) U[k / 3][k % 3] = {r[2 * k], r[2 * k + 1]};
+    reconstruct_row2(U);
+  }
+};
+template <> struct LinkIO<F16> : LinkIO16<F16> {};
+template <> struct LinkIO<BF16> : LinkIO16<BF16> {};
+
+// ---------------------------------------------------------------------------
+// 5th-dimension coefficients of one right-hand side (built on the host).
+//   M_phi = b5 + c5 P5,  M5 = alpha + beta P5,  kappa = beta / alpha,
+//   M5^-1 on one chirality: y_0 = (x_0 + sum_{k>=1} (-kappa)^k (-mq) x_{L5-k}) * inv_c,
+//   y_i = x_i - kappa y_{i-1}, result y * inv_alpha, inv_c = 1/(1 + mq (-kappa)^L5).
+// ---------------------------------------------------------------------------
+struct Coef5 {
+  double b5, c5, mq, alpha, beta, kappa, inv_alpha, inv_c;
+};
+
+// CG scalars of one right-hand side, resident on the device.
+struct CGState {
+  int active;   // 1: iterate; 0: frozen (waiting for the host) or finished
+  int flags;    // CG_FLAG_*
+  int iters;
+  int max_iter;
+  double rho;       // |r|^2 of the current residual
+  double rho_new;   // |r|^2 after the latest update
+  double pq;        // <p, A p>
+  double alpha, beta;
+  double rmax;      // max |r| since the last reliable update
+  double bb;        // |b|^2
+  double tol2;      // tol^2 |b|^2
+  double delta;     // reliable-update threshold (0: only at convergence)
+};
+
+enum : int {
+  CG_FLAG_UPDATE = 1,     // host: recompute the FP64 residual
+  CG_FLAG_BREAKDOWN = 2,  // <p, Ap> <= 0
+  CG_FLAG_NAN = 4,
+  CG_FLAG_MAXIT = 8,
+};
+
+}  // namespace mdwf

@@ -1,0 +1,128 @@
+// Host-side objects of libmdwf (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mdwf.h"
+#include "kernels.h"
+
+namespace mdwf {
+
+// grow-only device buffer
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+struct ProfRec {
+  int cls;
+  double bytes;
+  hipEvent_t e0, e1;
+};
+
+// one fused-operator program (see DslashArgs)
+struct Prog {
+  bool hop, dag, pro;
+  int c1, c2, aux, reduce;
+  double coef;
+  int out_par;
+};
+
+}  // namespace mdwf
+
+struct mdwf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  // profiling
+  bool prof = false;
+  std::vector<mdwf::ProfRec> pending;
+  std::vector<hipEvent_t> events;
+  int64_t prof_launches[MDWF_PROF_NCLASS] = {};
+  double prof_ms[MDWF_PROF_NCLASS] = {};
+  double prof_bytes[MDWF_PROF_NCLASS] = {};
+  // autotuner: key -> log2 of sites per workgroup
+  int tune_mode = 0;
+  std::map<std::string, int> tune;
+  std::map<std::string, float> tune_ms;
+  // device scratch
+  mdwf::DevBuf tables;     // pointer tables / small arrays, bump-allocated per call
+  void* tables_host = nullptr;  // pinned mirror of `tables`
+  size_t tables_used = 0;
+  hipEvent_t tables_ev = nullptr;  // recorded after the latest table upload
+  mdwf::DevBuf partials_d; // dslash 16-site tile partials
+  mdwf::DevBuf partials_b; // blas block partials
+  mdwf::DevBuf states;     // CGState per fused slot
+  mdwf::DevBuf coefs;      // Coef5 per slot
+  mdwf::DevBuf red_out;    // reduced doubles
+  mdwf::DevBuf tmp64[3];   // FP64 half-field temporaries (setup, updates, finalize)
+  mdwf::DevBuf dws;        // operator workspace of mdwf_dslash
+  double* red_host = nullptr;  // pinned
+  size_t red_host_n = 0;
+  mdwf::CGState* st_host = nullptr;  // pinned
+  size_t st_host_n = 0;
+};
+
+struct mdwf_gauge {
+  mdwf_ctx* ctx = nullptr;
+  int L[4] = {0, 0, 0, 0};
+  int Vh = 0;
+  void* data[4] = {nullptr, nullptr, nullptr, nullptr};  // per precision
+  size_t bytes = 0;
+};
+
+struct mdwf_job {
+  mdwf_ctx* ctx = nullptr;
+  const mdwf_gauge* g = nullptr;
+  mdwf_action act{};
+  mdwf_cg_opts opts{};
+  int nrhs = 0;
+  mdwf::Geom geom{};
+  int ps = 0, px = 0;  // inner spinor precision, inner solution precision
+  const char* eta = nullptr;
+  char* psi = nullptr;
+  size_t user_bytes = 0;  // bytes of one user-layout RHS
+  mdwf::Coef5 coef{};
+  void* block = nullptr;
+  size_t block_bytes = 0;
+  std::vector<char*> fx, fr, fp, fq, ft, fv, fxh;
+  std::vector<mdwf::CGState> st;
+  std::vector<mdwf_cg_stats> stats;
+  std::vector<int> finished;
+  double t0 = 0;
+  double bytes_iter = 0, flops_iter = 0;  // model, per RHS per iteration
+};
+
+namespace mdwf {
+
+// error helpers
+mdwf_status set_err(mdwf_ctx* c, mdwf_status s, const char* fmt, ...);
+mdwf_status hip_err(mdwf_ctx* c, hipError_t e, const char* what);
+
+// validation
+mdwf_status check_action_msg(const mdwf_action* a, std::string& msg);
+Geom make_geom(const mdwf_action* a);
+Coef5 make_coef(const mdwf_action* a);
+
+// device memory
+mdwf_status ensure(mdwf_ctx* c, DevBuf& b, size_t n);
+void release(DevBuf& b);
+// upload a pointer table / small array (stream-ordered); returns device address
+char* const* upload_table(mdwf_ctx* c, const std::vector<const void*>& ptrs);
+void* upload_bytes(mdwf_ctx* c, const void* data, size_t n);
+void reset_tables(mdwf_ctx* c);
+
+// launches with profiling
+hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* g, const Geom& geom, int prec, const Prog& pr,
+                    char* const* in, char* const* aux, char* const* out, const Coef5* coef_d, int nslots,
+                    const int* active, int active_stride, double* partials, int ntiles, int cls, bool tunable);
+void prof_begin(mdwf_ctx* c, hipEvent_t* e0);
+void prof_end(mdwf_ctx* c, int cls, double bytes, hipEvent_t e0);
+
+}  // namespace mdwf

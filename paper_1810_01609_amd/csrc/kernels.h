@@ -1,0 +1,106 @@
+// Launch interface of the libmdwf HIP kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "dev_common.h"
+
+namespace mdwf {
+
+// Fifth-dimension chains applied to whole columns of a site.
+enum Chain : int {
+  CH_NONE = 0,
+  CH_M5INV = 1,
+  CH_M5INV_DAG = 2,
+  CH_MPHI = 3,
+  CH_MPHI_DAG = 4,
+  CH_M5 = 5,
+  CH_M5_DAG = 6,
+  CH_MPHI_M5INV = 7,        // M_phi M5^-1
+  CH_MPHIDAG_M5INVDAG = 8,  // M_phi^T M5^-T
+};
+
+// Term added to coef_y * (chained hop result).
+enum AuxMode : int {
+  AUX_NONE = 0,
+  AUX_PLAIN = 1,  // + aux
+  AUX_M5 = 2,     // + M5 aux
+  AUX_M5DAG = 3,  // + M5^T aux
+};
+
+// out = c2( coef_y * c1( H (or H^dag) ( M_phi in if PRO ) ) + auxterm )
+// with an optional |.|^2 reduction of the value before c2.
+struct DslashArgs {
+  Geom g;
+  int out_par;
+  const char* gauge;       // gauge field of this precision
+  char* const* in;         // [nslots] input half-fields (parity 1-out_par; out_par if no hop)
+  char* const* aux;        // [nslots] or nullptr
+  char* const* out;        // [nslots]
+  const Coef5* coef;       // [nslots]
+  const int* active;       // nullptr or active flag of slot i at active[i*active_stride]
+  int active_stride;
+  double* partials;        // [nslots][ntiles] (16-site tiles) when reduce
+  int ntiles;
+  int nslots;
+  int nblk;                // filled by the launcher
+  int cb_log2;             // filled by the launcher
+  int lds_chain_bytes;     // filled by the launcher
+  int c1, c2, aux_mode, reduce;
+  double coef_y;
+};
+
+hipError_t dslash_launch(DslashArgs A, int prec, bool hop, bool dag, bool pro, int cb_log2, hipStream_t st);
+size_t dslash_lds_bytes(const DslashArgs& A, int prec, int cb_log2);
+int dslash_max_threads(int prec);
+
+// ---- BLAS-1 / reductions (one thread per 4D site, loop over s) ------------
+struct BlasArgs {
+  Geom g;
+  char* const* a;   // [nslots]
+  char* const* b;
+  char* const* c;
+  char* const* d;
+  CGState* st;      // [nslots] (CG kernels)
+  double* partials; // [nslots][nblk]
+  int nblk;         // filled by launcher
+  int nslots;
+  double ca, cb;    // coefficients for axpby
+};
+constexpr int kBlasThreads = 256;
+
+// CG: x += alpha p, r -= alpha q, partials of |r|^2.   a=x(px) b=p c=r d=q (ps)
+hipError_t blas_cg_xr(BlasArgs A, int px, int ps, hipStream_t st);
+// CG: p = r + beta p.   a=p b=r
+hipError_t blas_cg_p(BlasArgs A, int ps, hipStream_t st);
+// out = ca * in + cb * out  (cb == 0: out is not read).  a=in(pin) b=out(pout);
+// partials of |out|^2 if A.partials.
+hipError_t blas_axpby(BlasArgs A, int pin, int pout, hipStream_t st);
+// partials of |a - b|^2 (b may be nullptr table: |a|^2).  both precision p
+hipError_t blas_norm_diff(BlasArgs A, int p, hipStream_t st);
+int blas_nblk(const Geom& g);
+
+// ---- scalar kernels (one workgroup per slot, fixed summation order) -------
+// out[i] = sum_j partials[i*n + j]
+hipError_t scalar_reduce(const double* partials, int n, int nslots, double* out, hipStream_t st);
+// alpha = rho / <p,Ap>, with breakdown / NaN checks
+hipError_t scalar_cg_alpha(CGState* st_, const double* partials, int n, int nslots, hipStream_t st);
+// rho_new = |r|^2; freeze for the host or form beta
+hipError_t scalar_cg_beta(CGState* st_, const double* partials, int n, int nslots, hipStream_t st);
+
+// ---- layout, precision, sources --------------------------------------------
+// user complex128 full field [s][t][z][y][x][spin][col] -> half-field of parity par (prec p)
+hipError_t layout_user_to_half(const Geom& g, const char* const* user, char* const* half, int par, int p,
+                               int nslots, hipStream_t st);
+// half-field (prec p; nullptr entry in table: zeros) -> user sites of parity par
+hipError_t layout_half_to_user(const Geom& g, const char* const* half, char* const* user, int par, int p,
+                               int nslots, hipStream_t st);
+// user gauge complex128 [t][z][y][x][mu][3][3] (device) -> internal 12-real, prec p
+hipError_t layout_gauge(const Geom& g, const double* user, char* out, int p, hipStream_t st);
+hipError_t fill_zero(void* ptr, size_t bytes, hipStream_t st);
+hipError_t source_point(const Geom& g, double* eta, const int x0[4], int spin, int colour, hipStream_t st);
+hipError_t source_z2(const Geom& g, double* eta, uint64_t seed, int rhs_index, hipStream_t st);
+
+}  // namespace mdwf

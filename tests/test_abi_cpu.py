@@ -1,0 +1,80 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+the header declares, and host-only validation behaves as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1810_01609_amd import mdwf as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mdwf.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"MDWF_API\s+[\w\s\*]*?\b(mdwf_\w+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 20
+    lib = M.lib()
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in mdwf.h but not exported"
+    # the binding declares a signature for each of them
+    assert set(names) <= set(M._SIGS), set(names) - set(M._SIGS)
+
+
+def test_abi_version():
+    assert M.lib().mdwf_abi_version() == 1
+
+
+@pytest.mark.parametrize(
+    "kw,frag",
+    [
+        (dict(L=(3, 4, 4, 4), L5=4), "Lx must be even"),
+        (dict(L=(4, 1, 4, 4), L5=4), "Ly must be >= 2"),
+        (dict(L=(4, 4, 4, 4), L5=0), "L5 must be in"),
+        (dict(L=(4, 4, 4, 4), L5=33), "L5 must be in"),
+        (dict(L=(4, 4, 4, 4), L5=4, mq=-0.1), "mq must be >= 0"),
+        (dict(L=(4, 4, 4, 4), L5=4, b5=float("nan")), "finite"),
+        (dict(L=(4, 4, 4, 4), L5=4, t_antiperiodic=2), "t_antiperiodic"),
+    ],
+)
+def test_check_action_rejects(kw, frag):
+    act = M.Action.make(**kw)
+    st, msg = M.check_action(act)
+    assert st == M.EINVAL
+    assert frag in msg
+
+
+def test_check_action_accepts_benchmark_configs():
+    import mdwf_synth as S
+
+    for name, c in S.CONFIGS.items():
+        act = M.Action.make(c["L"], c["L5"], c["b5"], c["c5"], c["M5"], c["mq"])
+        assert M.check_action(act) == (M.OK, ""), name
+
+
+def test_job_footprint_model():
+    act = M.Action.make((32, 32, 32, 64), 12, mq=0.005)
+    Vh = 32 * 32 * 32 * 64 // 2
+    ne = Vh * 12
+    f64 = M.job_footprint(act, M.CGOpts.make(inner="f64"), 1)
+    f32 = M.job_footprint(act, M.CGOpts.make(inner="f32"), 12)
+    f16 = M.job_footprint(act, M.CGOpts.make(inner="f16"), 12)
+    # FP64: r p q t v x (6 fields) + 3 context temporaries
+    assert f64 >= 9 * ne * 192
+    # FP32 per RHS: 5 FP32 work fields + FP32 x + FP64 xh
+    assert f32 >= 12 * (6 * ne * 96 + ne * 192)
+    assert f16 < f32
+    assert M.job_footprint(act, M.CGOpts.make(inner="f64"), 0) == 0
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(M, "_lib", None)
+    monkeypatch.setattr(M, "LIB_PATH", "/nonexistent/libmdwf.so")
+    with pytest.raises(M.MDWFError):
+        M.lib()
