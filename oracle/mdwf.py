@@ -496,7 +496,8 @@ def z2_noise(act, seed, rhs=0):
         z = z ^ (z >> np.uint64(31))
     re = 1.0 - 2.0 * (z & np.uint64(1)).astype(np.float64)
     im = 1.0 - 2.0 * ((z >> np.uint64(1)) & np.uint64(1)).astype(np.float64)
-    xi = (re + 1j * im) / np.sqrt(2.0)
+    # 1/sqrt(2) correctly rounded (sqrt is correctly rounded; 1/np.sqrt(2) is not)
+    xi = (re + 1j * im) * np.sqrt(0.5)
     return xi.reshape(Lt, Lz, Ly, Lx, 4, 3)
 
 

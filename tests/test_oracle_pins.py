@@ -333,9 +333,10 @@ def test_z2_noise_vectorised_matches_scalar():
     n = flat.size
     for k in range(n):
         z = O.splitmix64(1234567, n + k)
-        expect = ((-1.0 if z & 1 else 1.0) + 1j * (-1.0 if z & 2 else 1.0)) / np.sqrt(2)
+        expect = ((-1.0 if z & 1 else 1.0) + 1j * (-1.0 if z & 2 else 1.0)) * 0.7071067811865476
         assert flat[k] == expect
     assert np.allclose(np.abs(flat), 1.0)
+    assert 0.7071067811865476 == float.fromhex('0x1.6a09e667f3bcdp-1')  # nearest double to 1/sqrt(2)
 
 
 def test_point_source_wall_injection():
