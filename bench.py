@@ -1,0 +1,236 @@
+"""Benchmark: Moebius domain-wall propagator solves on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+
+One step is one pass of the whole solve path over one right-hand side of the
+workload: complex Z2 source generated on the device, even-odd source
+preparation, mixed-precision CG (FP32 inner iteration with FP64 reliable
+updates and FP64 reductions) to |b - A x| <= 1e-10 |b|, reconstruction of the
+odd half and the FP64 full-5D residual check.  The gauge field is resident
+in HBM before timing starts.  `value` is solves per second over the timed
+steps; the JSON line also carries the per-step latency percentiles, the
+plain FP64 solver on the same input, the fused stencil kernel's roofline
+(algorithmic bytes per launch / its average HIP-event duration) and the CPU
+oracle's rate on a bounded sample of the same workload.
+
+The workload (default c2): lattice 16^3 x 32, L5 = 12, b5 = 1.5, c5 = 0.5,
+M5 = 1.3, m_q = 0.02, links exp(i 0.2 H) seed 2, Z2 source seed 1002.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("dslash.hip", "dev_common.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_1810_01609_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the fused stencil kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"dslash_{workload}_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_sha") != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    return d.get("traffic_bytes_per_launch"), d.get("note", "")
+
+
+def cpu_baseline(cfg, gpu_iters_f64: int):
+    """The oracle as it stands, timed on a bounded sample of the workload.
+
+    Each of the oracle's building blocks is applied once to a field on the
+    full lattice (one 4D hop H, one M5^-1, one M_phi: ~30 s of CPU work);
+    the solve time is then composed from how often the oracle's even-odd
+    CGNR calls them: per iteration 4 hops, 4 M5^-1 and 4 M_phi (M^ and M^+),
+    plus setup (source preparation and b = M^+ eta^: 3 hops, 4 M5^-1,
+    3 M_phi), times the FP64 iteration count of the same solve.
+    """
+    import mdwf_synth as S
+    import oracle as O
+
+    act = O.Action(cfg["L"], cfg["L5"], cfg["b5"], cfg["c5"], cfg["M5"], cfg["mq"])
+    U = S.gauge_field(cfg["L"], cfg["eps"], cfg["seed"])
+    x = S.random_spinor(cfg["L"], cfg["L5"], 7)
+    t = {}
+    for name, fn in (("hop", lambda: O.hop(U, x, act)), ("m5_inv", lambda: O.m5_inv(x, act)),
+                     ("m_phi", lambda: O.m_phi(x, act))):
+        t0 = time.perf_counter()
+        fn()
+        t[name] = time.perf_counter() - t0
+    per_iter = 4 * t["hop"] + 4 * t["m5_inv"] + 4 * t["m_phi"]
+    setup = 3 * t["hop"] + 4 * t["m5_inv"] + 3 * t["m_phi"]
+    t_solve = setup + per_iter * gpu_iters_f64
+    return {
+        "value": 1.0 / t_solve,
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle hop, M5^-1 and M_phi each applied once (NumPy FP64, one thread) on the full "
+                   f"{cfg['L'][0]}^3x{cfg['L'][3]} L5={cfg['L5']} lattice; solve time composed as setup + "
+                   f"{gpu_iters_f64} CGNR iterations x (4 hop + 4 M5^-1 + 4 M_phi), the oracle's own call "
+                   f"counts, with the FP64 iteration count of the same solve"),
+        "component_seconds": t,
+        "seconds_per_iteration": per_iter,
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--inner", default="f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-f64", action="store_true", help="skip the plain FP64 reference solve (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of known size (for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver runs each "
+              f"propagator on a single MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if args.copy_calibration:
+        n = 1 << 28  # 2 GiB of float64
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 8, "launches": 5}))
+        return
+
+    import mdwf_synth as S
+    from paper_1810_01609_amd import mdwf as M
+
+    cfg = S.CONFIGS[args.workload]
+    L, L5 = cfg["L"], cfg["L5"]
+    act = M.Action.make(L, L5, cfg["b5"], cfg["c5"], cfg["M5"], cfg["mq"])
+    U = S.gauge_field(L, cfg["eps"], cfg["seed"])
+    ctx = M.Context(0)
+    g = ctx.gauge_load(L, U, precs=("f64", args.inner))
+    shape = act.spinor_shape()
+    eta = torch.zeros(shape, dtype=torch.complex128, device="cuda")
+    psi = torch.zeros_like(eta)
+    opts = M.CGOpts.make(tol=1e-10, inner=args.inner, delta=0.1)
+    opts64 = M.CGOpts.make(tol=1e-10, inner="f64")
+
+    def step(o):
+        if cfg["source"] == "z2":
+            ctx.source_z2(act, cfg["z2_seed"], 0, eta)
+        else:
+            ctx.source_point(act, (0, 0, 0, 0), 0, 0, eta)
+        return ctx.solve(g, act, o, eta, psi)[0]
+
+    # plain FP64 CG on the same input (reference rate and iteration count)
+    st64, t64 = {"iters": 0, "rel_res_full": None}, float("nan")
+    if not args.skip_f64:
+        step(opts64)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st64 = step(opts64)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t
+
+    for _ in range(args.warmup):
+        step(opts)
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    ctx.profile_reset()
+    lat = []
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        stats.append(step(opts))
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = {k: ctx.profile_read(c) for k, c in
+            (("dslash", M.PROF_DSLASH_INNER), ("dslash_f64", M.PROF_DSLASH_F64), ("blas", M.PROF_BLAS),
+             ("scalar", M.PROF_SCALAR), ("other", M.PROF_OTHER))}
+    ctx.profile_enable(False)
+    ok = all(s["converged"] == 1 and s["rel_res_normal"] <= 1e-10 for s in stats)
+
+    d = prof["dslash"]
+    avg_ms = d["ms"] / max(d["launches"], 1)
+    bytes_per_launch = d["bytes"] / max(d["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic, traffic_note = measured_traffic(args.workload)
+
+    line = {
+        "metric": "MDWF CG solves/s at rel-res 1e-10; Dslash HBM GB/s; p50/p99 solve latency",
+        "value": args.steps / elapsed if ok else 0.0,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{args.workload}: {L[0]}x{L[1]}x{L[2]}x{L[3]} L5={L5} Moebius b5={cfg['b5']} "
+                         f"c5={cfg['c5']} M5={cfg['M5']} mq={cfg['mq']}, links exp(i{cfg['eps']}H) "
+                         f"seed {cfg['seed']}, {cfg['source']} source, even-odd CGNR to 1e-10, "
+                         f"{args.inner} inner + f64 reliable updates"),
+            "lattice": list(L), "L5": L5, "nrhs": 1, "inner": args.inner, "tol": 1e-10,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "dslash5_kernel (fused hop + 5th-dim, inner precision)",
+            "avg_launch_ms": avg_ms,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "launches": d["launches"],
+            "traffic_note": traffic_note,
+        },
+        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
+        "solve": {
+            "iters": stats[-1]["iters"], "reliable_updates": stats[-1]["reliable_updates"],
+            "rel_res_normal": stats[-1]["rel_res_normal"], "rel_res_full": stats[-1]["rel_res_full"],
+            "converged_all": ok,
+        },
+        "f64_plain_cg": {"solves_per_s": 1.0 / t64 if t64 == t64 else None, "iters": st64["iters"],
+                         "rel_res_full": st64["rel_res_full"]},
+        "kernel_time_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()},
+    }
+    if not args.no_cpu_baseline and not args.skip_f64:
+        line["cpu_baseline"] = cpu_baseline(cfg, st64["iters"])
+    g.free()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -187,8 +187,9 @@ def test_dslash_rejects_bad_arguments(ctx):
     x = empty_like_dev(act.spinor_shape())
     bad = M.Action.make((4, 4, 4, 4), 8)  # lattice differs from the gauge field
     with pytest.raises(M.MDWFError) as e:
-        ctx.dslash(g, bad, M.OP_D, "f64", x, empty_like_dev(bad.spinor_shape()))
+        ctx.dslash(g, bad, M.OP_D, "f64", empty_like_dev(bad.spinor_shape()), empty_like_dev(bad.spinor_shape()))
     assert e.value.status == M.EINVAL
+    assert "lattice" in str(e.value)
     with pytest.raises(M.MDWFError):
         ctx.dslash(g, act, M.OP_D, "f64", x, x)  # in == out
     with pytest.raises(M.MDWFError):
