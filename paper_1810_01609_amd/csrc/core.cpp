@@ -219,10 +219,11 @@ void prof_end(mdwf_ctx* c, int cls, double bytes, hipEvent_t e0) {
 // tiles, so tuning never changes results.  Launches whose output aliases an
 // input are not tuned (no backup/restore of destroyed data is needed then).
 // ---------------------------------------------------------------------------
-static std::string tune_key(const Geom& g, int prec, const Prog& p, int nslots) {
+static std::string tune_key(const Geom& g, int prec, const Prog& p, int nslots, bool cg) {
   char buf[256];
-  snprintf(buf, sizeof(buf), "dslash5 p%d h%d d%d pr%d c%d.%d a%d r%d L%dx%dx%dx%d L5=%d n%d gfx950", prec,
-           (int)p.hop, (int)p.dag, (int)p.pro, p.c1, p.c2, p.aux, p.reduce, g.Lx, g.Ly, g.Lz, g.Lt, g.L5, nslots);
+  snprintf(buf, sizeof(buf), "dslash5 p%d h%d d%d pr%d c%d.%d a%d r%d u%d L%dx%dx%dx%d L5=%d n%d gfx950", prec,
+           (int)p.hop, (int)p.dag, (int)p.pro, p.c1, p.c2, p.aux, p.reduce, (int)cg, g.Lx, g.Ly, g.Lz, g.Lt, g.L5,
+           nslots);
   return buf;
 }
 
@@ -241,10 +242,12 @@ static void candidates(const Geom& g, int prec, const DslashArgs& A, std::vector
   if (dflt < 0 && !out.empty()) dflt = out.front();
 }
 
-static double prog_bytes(const Geom& g, int prec, const Prog& p, int nslots) {
+static double prog_bytes(const Geom& g, int prec, const Prog& p, int nslots, bool cg) {
   const double ne = (double)g.Vh * g.L5;
   const double sb = spinor_site_bytes(prec);
+  // in + out (+ aux); the fused CG update reads p, r, x and writes r, x instead of out
   double per = 2.0 + (p.aux != AUX_NONE ? 1.0 : 0.0);
+  if (cg) per += 2.0 + 2.0 * spinor_site_bytes(prec == F64 ? F64 : F32) / sb;
   double b = nslots * ne * sb * per;
   if (p.hop) b += 8.0 * g.Vh * 12.0 * link_real_bytes(prec);
   return b;
@@ -252,7 +255,8 @@ static double prog_bytes(const Geom& g, int prec, const Prog& p, int nslots) {
 
 hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int prec, const Prog& pr,
                     char* const* in, char* const* aux, char* const* out, const Coef5* coef_d, int nslots,
-                    const int* active, int active_stride, double* partials, int ntiles, int cls, bool tunable) {
+                    const int* active, int active_stride, double* partials, int ntiles, int cls, bool tunable,
+                    const CgFuse* fuse) {
   DslashArgs A{};
   A.g = geom;
   A.out_par = pr.out_par;
@@ -271,12 +275,21 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int pre
   A.aux_mode = pr.aux;
   A.reduce = pr.reduce;
   A.coef_y = pr.coef;
+  if (fuse != nullptr) {
+    A.cg_update = 1;
+    A.cg_x = fuse->x;
+    A.cg_r = fuse->r;
+    A.cg_p = fuse->p;
+    A.cg_st = fuse->st;
+  }
   std::vector<int> cand;
   int dflt = 4;
   candidates(geom, prec, A, cand, dflt);
   if (cand.empty()) return hipErrorInvalidValue;
   int lg = dflt;
-  const std::string key = tune_key(geom, prec, pr, nslots);
+  const std::string key = tune_key(geom, prec, pr, nslots, fuse != nullptr);
+  // the fused CG update is destructive (x, r in place): never tuned on live data
+  if (fuse != nullptr) tunable = false;
   auto it = c->tune.find(key);
   if (it != c->tune.end()) {
     lg = it->second;
@@ -312,7 +325,7 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int pre
   hipEvent_t ev;
   prof_begin(c, &ev);
   hipError_t e = dslash_launch(A, prec, pr.hop, pr.dag, pr.pro, lg, c->stream);
-  prof_end(c, cls, prog_bytes(geom, prec, pr, nslots), ev);
+  prof_end(c, cls, prog_bytes(geom, prec, pr, nslots, fuse != nullptr), ev);
   return e;
 }
 

@@ -349,6 +349,27 @@ __global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
     for (int k = 0; k < 24; ++k) v[k] += w[k];
   }
 
+  if (A.cg_update) {
+    // x += alpha p, r -= alpha q with q = v; v becomes r for the reduction
+    constexpr int PX = P == F64 ? F64 : F32;
+    if (valid) {
+      const R alpha = (R)A.cg_st[slot].alpha;
+      R pv[24], rv[24];
+      typename PrecTraits<PX>::Real xv[24];
+      SpinorIO<P>::load(A.cg_p[slot], f, cb, s, pv);
+      SpinorIO<P>::load(A.cg_r[slot], f, cb, s, rv);
+      SpinorIO<PX>::load(A.cg_x[slot], f, cb, s, xv);
+#pragma unroll
+      for (int k = 0; k < 24; ++k) {
+        xv[k] += alpha * pv[k];
+        rv[k] -= alpha * v[k];
+        v[k] = rv[k];
+      }
+      SpinorIO<PX>::store(A.cg_x[slot], f, cb, s, xv);
+      SpinorIO<P>::store(A.cg_r[slot], f, cb, s, rv);
+    }
+  }
+
   if (A.reduce) {
     double loc = 0;
 #pragma unroll
@@ -378,7 +399,7 @@ __global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
     __syncthreads();
     lds_get(lds, CB, cbl, s, v);
   }
-  if (valid) SpinorIO<P>::store(A.out[slot], f, cb, s, v);
+  if (valid && !A.cg_update) SpinorIO<P>::store(A.out[slot], f, cb, s, v);
 }
 
 // ---------------------------------------------------------------------------

@@ -91,7 +91,7 @@ struct mdwf_job {
   mdwf::Coef5 coef{};
   void* block = nullptr;
   size_t block_bytes = 0;
-  std::vector<char*> fx, fr, fp, fq, ft, fv, fxh;
+  std::vector<char*> fx, fr, fp, ft, fv, fxh;
   std::vector<mdwf::CGState> st;
   std::vector<mdwf_cg_stats> stats;
   std::vector<int> finished;
@@ -118,10 +118,19 @@ char* const* upload_table(mdwf_ctx* c, const std::vector<const void*>& ptrs);
 void* upload_bytes(mdwf_ctx* c, const void* data, size_t n);
 void reset_tables(mdwf_ctx* c);
 
+// CG update fused into a stencil launch (see DslashArgs::cg_update)
+struct CgFuse {
+  char* const* x;
+  char* const* r;
+  char* const* p;
+  const CGState* st;
+};
+
 // launches with profiling
 hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* g, const Geom& geom, int prec, const Prog& pr,
                     char* const* in, char* const* aux, char* const* out, const Coef5* coef_d, int nslots,
-                    const int* active, int active_stride, double* partials, int ntiles, int cls, bool tunable);
+                    const int* active, int active_stride, double* partials, int ntiles, int cls, bool tunable,
+                    const CgFuse* fuse = nullptr);
 void prof_begin(mdwf_ctx* c, hipEvent_t* e0);
 void prof_end(mdwf_ctx* c, int cls, double bytes, hipEvent_t e0);
 

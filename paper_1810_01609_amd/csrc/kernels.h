@@ -50,6 +50,14 @@ struct DslashArgs {
   int lds_chain_bytes;     // filled by the launcher
   int c1, c2, aux_mode, reduce;
   double coef_y;
+  // CG update fused into the epilogue (cg_update = 1): with q the combined
+  // value, x += alpha p, r -= alpha q, and the reduction takes |r|^2; q and
+  // `out` are not written.  x is FP64 for an FP64 kernel, FP32 otherwise.
+  int cg_update;
+  char* const* cg_x;
+  char* const* cg_r;
+  char* const* cg_p;
+  const CGState* cg_st;
 };
 
 hipError_t dslash_launch(DslashArgs A, int prec, bool hop, bool dag, bool pro, int cb_log2, hipStream_t st);

@@ -54,7 +54,7 @@ SlotLayout slot_layout(const Geom& g, int ps) {
   L.fs = round_up(spinor_field_bytes(ps, g.L5, g.Vh), 256);
   L.fx = round_up(spinor_field_bytes(inner_x_prec(ps), g.L5, g.Vh), 256);
   L.fxh = ps == F64 ? 0 : round_up(spinor_field_bytes(F64, g.L5, g.Vh), 256);
-  L.total = 5 * L.fs + L.fx + L.fxh;
+  L.total = 4 * L.fs + L.fx + L.fxh;
   return L;
 }
 
@@ -63,8 +63,9 @@ void iter_model(const Geom& g, int ps, double& bytes, double& flops) {
   const double ne = (double)g.Vh * g.L5;
   const double sb = spinor_site_bytes(ps), sx = spinor_site_bytes(inner_x_prec(ps));
   const double links = 8.0 * g.Vh * 12.0 * link_real_bytes(ps);
-  // 4 fused hops: 10 spinor transfers + 4 link sweeps; BLAS: x rw, p q r read, r write, p r read p write
-  bytes = ne * sb * 10 + 4 * links + ne * (2 * sx + 4 * sb) + ne * 3 * sb;
+  // A1 2, A2 3, B1 2, B2 with the fused update 5 spinor transfers + x read/write,
+  // 4 link sweeps; p = r + beta p 3 transfers
+  bytes = ne * sb * 12 + 2 * ne * sx + 4 * links + ne * 3 * sb;
   // hop 1320/site x4, M_phi 72 x3, M5^-1 96 x4, M5 72, xpay 48 x2, CG BLAS 192
   flops = ne * (4 * 1320.0 + 3 * 72 + 4 * 96 + 72 + 2 * 48 + 192);
 }
@@ -340,7 +341,6 @@ extern "C" mdwf_status mdwf_job_begin(mdwf_ctx* c, const mdwf_gauge* g, const md
   for (int r = 0; r < nrhs; ++r) {
     j->fr.push_back(p); p += L.fs;
     j->fp.push_back(p); p += L.fs;
-    j->fq.push_back(p); p += L.fs;
     j->ft.push_back(p); p += L.fs;
     j->fv.push_back(p); p += L.fs;
     j->fx.push_back(p); p += L.fx;
@@ -437,7 +437,7 @@ extern "C" mdwf_status mdwf_job_step(mdwf_ctx* c, mdwf_job* const* jobs, int32_t
   (void)hipSetDevice(c->device);
   reset_tables(c);
   const Geom geom = j0->geom;
-  const int ps = j0->ps, px = j0->px;
+  const int ps = j0->ps;
   const int ntiles = (geom.Vh + 15) / 16;
   const int nblk = blas_nblk(geom);
   mdwf_status st = MDWF_OK;
@@ -454,26 +454,26 @@ extern "C" mdwf_status mdwf_job_step(mdwf_ctx* c, mdwf_job* const* jobs, int32_t
   if (slots.empty() || iters == 0) return MDWF_OK;
 
   using Tab = char* const*;
-  Tab X = nullptr, R = nullptr, P = nullptr, Q = nullptr, T = nullptr, V = nullptr;
+  Tab X = nullptr, R = nullptr, P = nullptr, T = nullptr, V = nullptr;
   const Coef5* coef_d = nullptr;
   CGState* S_d = nullptr;
   double* pd = nullptr;
   double* pb = nullptr;
   auto build = [&]() -> mdwf_status {
     const int n = (int)slots.size();
-    std::vector<const void*> x(n), r(n), p(n), q(n), t(n), v(n);
+    std::vector<const void*> x(n), r(n), p(n), t(n), v(n);
     std::vector<Coef5> cf(n);
     for (int i = 0; i < n; ++i) {
       mdwf_job* j = slots[i].job;
       const int k = slots[i].r;
       x[i] = j->fx[k]; r[i] = j->fr[k]; p[i] = j->fp[k];
-      q[i] = j->fq[k]; t[i] = j->ft[k]; v[i] = j->fv[k];
+      t[i] = j->ft[k]; v[i] = j->fv[k];
       cf[i] = j->coef;
     }
     X = upload_table(c, x); R = upload_table(c, r); P = upload_table(c, p);
-    Q = upload_table(c, q); T = upload_table(c, t); V = upload_table(c, v);
+    T = upload_table(c, t); V = upload_table(c, v);
     coef_d = static_cast<const Coef5*>(upload_bytes(c, cf.data(), n * sizeof(Coef5)));
-    if (!X || !R || !P || !Q || !T || !V || !coef_d) return set_err(c, MDWF_EHIP, "mdwf_job_step: table upload");
+    if (!X || !R || !P || !T || !V || !coef_d) return set_err(c, MDWF_EHIP, "mdwf_job_step: table upload");
     mdwf_status s2 = ensure(c, c->states, n * sizeof(CGState));
     if (s2 == MDWF_OK) s2 = ensure(c, c->partials_d, (size_t)n * ntiles * sizeof(double));
     if (s2 == MDWF_OK) s2 = ensure(c, c->partials_b, (size_t)n * nblk * sizeof(double));
@@ -514,32 +514,25 @@ extern "C" mdwf_status mdwf_job_step(mdwf_ctx* c, mdwf_job* const* jobs, int32_t
       if (e == hipSuccess)
         e = run_prog(c, j0->g, geom, ps, prog_A2(true, true), T, P, V, coef_d, n, act, stride, pd, ntiles,
                      MDWF_PROF_DSLASH_INNER, true);
-      if (e == hipSuccess)
-        e = run_prog(c, j0->g, geom, ps, prog_B1(), V, nullptr, T, coef_d, n, act, stride, nullptr, 0,
-                     MDWF_PROF_DSLASH_INNER, true);
-      if (e == hipSuccess)
-        e = run_prog(c, j0->g, geom, ps, prog_B2(), T, V, Q, coef_d, n, act, stride, nullptr, 0,
-                     MDWF_PROF_DSLASH_INNER, true);
       hipEvent_t ev;
-      if (e == hipSuccess) {
+      if (e == hipSuccess) {  // alpha = rho / <p, A p>, <p, A p> = |M^ p|^2 from A2
         prof_begin(c, &ev);
         e = scalar_cg_alpha(S_d, pd, ntiles, n, c->stream);
         prof_end(c, MDWF_PROF_SCALAR, 0, ev);
       }
-      if (e == hipSuccess) {
-        BlasArgs B{};
-        B.g = geom;
-        B.nslots = n;
-        B.a = X; B.b = P; B.c = R; B.d = Q;
-        B.st = S_d;
-        B.partials = pb;
-        prof_begin(c, &ev);
-        e = blas_cg_xr(B, px, ps, c->stream);
-        prof_end(c, MDWF_PROF_BLAS, n * ne * (2.0 * spinor_site_bytes(px) + 4.0 * spinor_site_bytes(ps)), ev);
+      if (e == hipSuccess)
+        e = run_prog(c, j0->g, geom, ps, prog_B1(), V, nullptr, T, coef_d, n, act, stride, nullptr, 0,
+                     MDWF_PROF_DSLASH_INNER, true);
+      if (e == hipSuccess) {  // q = M^+ M^ p, fused with x += alpha p, r -= alpha q, |r|^2
+        const CgFuse fz{X, R, P, S_d};
+        Prog b2 = prog_B2();
+        b2.reduce = 1;
+        e = run_prog(c, j0->g, geom, ps, b2, T, V, T, coef_d, n, act, stride, pd, ntiles, MDWF_PROF_DSLASH_INNER,
+                     false, &fz);
       }
       if (e == hipSuccess) {
         prof_begin(c, &ev);
-        e = scalar_cg_beta(S_d, pb, nblk, n, c->stream);
+        e = scalar_cg_beta(S_d, pd, ntiles, n, c->stream);
         prof_end(c, MDWF_PROF_SCALAR, 0, ev);
       }
       if (e == hipSuccess) {

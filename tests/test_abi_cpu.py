@@ -65,10 +65,10 @@ def test_job_footprint_model():
     f64 = M.job_footprint(act, M.CGOpts.make(inner="f64"), 1)
     f32 = M.job_footprint(act, M.CGOpts.make(inner="f32"), 12)
     f16 = M.job_footprint(act, M.CGOpts.make(inner="f16"), 12)
-    # FP64: r p q t v x (6 fields) + 3 context temporaries
-    assert f64 >= 9 * ne * 192
-    # FP32 per RHS: 5 FP32 work fields + FP32 x + FP64 xh
-    assert f32 >= 12 * (6 * ne * 96 + ne * 192)
+    # FP64: r p t v x (5 fields) + 3 context temporaries
+    assert f64 >= 8 * ne * 192
+    # FP32 per RHS: 4 FP32 work fields + FP32 x + FP64 xh
+    assert f32 >= 12 * (5 * ne * 96 + ne * 192)
     assert f16 < f32
     assert M.job_footprint(act, M.CGOpts.make(inner="f64"), 0) == 0
 
