@@ -94,6 +94,85 @@ def cpu_baseline(cfg, gpu_iters_f64: int):
     }
 
 
+def serve_bench(args):
+    """c5: a Poisson stream of solves served with continuous batching."""
+    import mdwf_synth as S
+    from paper_1810_01609_amd.serve import GPUBackend, Request, merge_chunks, percentiles, serve_gpu, split_requests
+
+    vols = [(8, 8, 8, 16), (16, 16, 16, 32), (24, 24, 24, 48), (32, 32, 32, 64)]
+    trace = S.poisson_trace(args.requests, args.rate, 5, vols, [8, 12, 16], (0.005, 0.05), (1, 12))
+    reqs = [Request(id=d["id"], t_arrival=d["t_arrival"], volume=d["volume"], L5=d["L5"], mq=d["mq"],
+                    nsrc=d["nsrc"], seed=100000 + d["id"]) for d in trace]
+    parts = split_requests(reqs, args.max_rhs)
+    inner = args.inner or "f16"
+    be = GPUBackend(vols, gauge_eps=0.2, gauge_seeds={v: 11 + i for i, v in enumerate(vols)}, inner=inner)
+    budget = int(args.hbm_budget_gb * 1e9) - be.resident_bytes
+    sched, _, wall = serve_gpu(parts, be, budget, iters_per_step=args.iters_per_step,
+                               max_slots_per_lane=args.max_slots)
+    be.close()
+    done = merge_chunks(sched.done)
+    nrhs = sum(r.nsrc for r in done)
+    ok = all(s.get("converged") == 1 for r in done for s in r.stats)
+    p = percentiles(done)
+    line = {
+        "metric": "MDWF CG solves/s at rel-res 1e-10; Dslash HBM GB/s; p50/p99 solve latency",
+        "value": nrhs / wall if ok else 0.0,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": len(done), "warmup": 0, "ms_per_step": 1e3 * wall / max(len(done), 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": inner, "data": "synthetic",
+        "config": {"workload": (f"c5: Poisson stream of {args.requests} requests at {args.rate}/s over volumes "
+                                f"{vols}, L5 in {{8,12,16}}, mq U[0.005,0.05], 1-12 Z2 sources, "
+                                f"chunks of <= {args.max_rhs} RHS, {inner} inner, continuous batching"),
+                   "budget_gb": budget / 1e9},
+        "latency_ms": p,
+        "rhs_completed": nrhs, "wall_s": wall, "peak_hbm_gb": sched.peak_used / 1e9, "converged_all": ok,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def dslash_bench(args):
+    """Stencil throughput: M^+M^ (the four fused launches of one CG
+    iteration, without the BLAS) applied repeatedly in each precision."""
+    import torch
+
+    import mdwf_synth as S
+    from paper_1810_01609_amd import mdwf as M
+
+    cfg = S.CONFIGS[args.workload]
+    L, L5 = cfg["L"], cfg["L5"]
+    nrhs = args.nrhs
+    act = M.Action.make(L, L5, cfg["b5"], cfg["c5"], cfg["M5"], cfg["mq"])
+    ctx = M.Context(0)
+    ctx.tune_mode(1 if args.tune else 0)
+    U = S.gauge_field(L, cfg["eps"], cfg["seed"])
+    g = ctx.gauge_load(L, U, precs=("f64", "f32", "f16", "bf16"))
+    del U
+    x = torch.zeros((nrhs,) + act.spinor_shape(), dtype=torch.complex128, device="cuda")
+    for r in range(nrhs):
+        ctx.source_z2(act, 7, r, x[r])
+    y = torch.zeros_like(x)
+    out = {}
+    for p in args.precs.split(","):
+        cls = M.PROF_DSLASH_F64 if p == "f64" else M.PROF_DSLASH_INNER
+        for _ in range(2):
+            ctx.dslash(g, act, M.OP_NORMAL, p, x, y, nrhs=nrhs)
+        ctx.profile_enable(True)
+        ctx.profile_reset()
+        for _ in range(args.steps):
+            ctx.dslash(g, act, M.OP_NORMAL, p, x, y, nrhs=nrhs)
+        d = ctx.profile_read(cls)
+        ctx.profile_enable(False)
+        avg = d["ms"] / d["launches"]
+        gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        out[p] = {"GB_per_s": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS, "avg_launch_ms": avg,
+                  "bytes_per_launch": d["bytes"] / d["launches"], "launches": d["launches"]}
+    g.free()
+    ctx.close()
+    print(json.dumps({"workload": args.workload, "lattice": list(L), "L5": L5, "nrhs": nrhs,
+                      "op": "M^+M^ (4 fused stencil launches)", "tuned": bool(args.tune), "dslash": out}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +182,16 @@ def main():
     ap.add_argument("--inner", default=None, help="inner precision (default: f32 for c1/c2, f16 for c3/c4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-f64", action="store_true", help="skip the plain FP64 reference solve (profiling runs)")
+    ap.add_argument("--requests", type=int, default=12, help="c5: requests in the trace")
+    ap.add_argument("--rate", type=float, default=20.0, help="c5: mean arrivals per second")
+    ap.add_argument("--max-rhs", type=int, default=4, help="c5: largest chunk of sources admitted at once")
+    ap.add_argument("--max-slots", type=int, default=16, help="c5: largest fused batch per lane")
+    ap.add_argument("--iters-per-step", type=int, default=25, help="c5: iterations between batch changes")
+    ap.add_argument("--hbm-budget-gb", type=float, default=240.0, help="c5: device memory for jobs")
+    ap.add_argument("--dslash-only", action="store_true", help="stencil throughput of M^+M^ per precision")
+    ap.add_argument("--precs", default="f64,f32,f16,bf16")
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--tune", action="store_true", help="enable the launch autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (for HBM counter scaling)")
     args = ap.parse_args()
@@ -121,6 +210,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": n * 8, "launches": 5}))
+        return
+
+    if args.workload == "c5":
+        serve_bench(args)
+        return
+    if args.dslash_only:
+        dslash_bench(args)
         return
 
     import mdwf_synth as S

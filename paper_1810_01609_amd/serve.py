@@ -37,6 +37,8 @@ class Request:
     mq: float
     nsrc: int
     seed: int = 0
+    parent: int = -1  # id of the request a chunk belongs to (-1: a whole request)
+    src_offset: int = 0  # index of the chunk's first source within its request
     # filled by the scheduler
     t_admit: float = -1.0
     t_done: float = -1.0
@@ -50,6 +52,38 @@ class Request:
     @property
     def latency(self):
         return self.t_done - self.t_arrival
+
+
+def split_requests(trace, max_rhs):
+    """Split requests with more than `max_rhs` sources into chunks that are
+    admitted and batched independently (a 12-source request on the largest
+    volume would otherwise have to hold the whole GPU).  Chunk ids are
+    (request id * 1000 + chunk index); `parent` names the request."""
+    out = []
+    for r in trace:
+        if r.nsrc <= max_rhs:
+            out.append(r)
+            continue
+        for k, off in enumerate(range(0, r.nsrc, max_rhs)):
+            out.append(Request(id=r.id * 1000 + k, t_arrival=r.t_arrival, volume=r.volume, L5=r.L5, mq=r.mq,
+                               nsrc=min(max_rhs, r.nsrc - off), seed=r.seed, parent=r.id, src_offset=off))
+    return out
+
+
+def merge_chunks(done):
+    """Per original request: arrival, first admission, last completion."""
+    by = {}
+    for r in done:
+        key = r.parent if r.parent >= 0 else r.id
+        if key not in by:
+            by[key] = Request(id=key, t_arrival=r.t_arrival, volume=r.volume, L5=r.L5, mq=r.mq, nsrc=0,
+                              seed=r.seed, t_admit=r.t_admit, t_done=r.t_done)
+        m = by[key]
+        m.nsrc += r.nsrc
+        m.t_admit = min(m.t_admit, r.t_admit)
+        m.t_done = max(m.t_done, r.t_done)
+        m.stats = m.stats + list(r.stats)
+    return list(by.values())
 
 
 class Scheduler:
@@ -236,7 +270,7 @@ class GPUBackend:
         psi = torch.zeros_like(eta)
         torch.cuda.synchronize(self.device)
         for k in range(req.nsrc):
-            ctx.source_z2(a, req.seed, k, eta[k])
+            ctx.source_z2(a, req.seed, req.src_offset + k, eta[k])
         job = ctx.job_begin(self.gauge[tuple(req.volume)], a, self.opts(), eta, psi, nrhs=req.nsrc)
         job.req = req
         job.psi = psi

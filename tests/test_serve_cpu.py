@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 import mdwf_synth as S
-from paper_1810_01609_amd.serve import Request, Scheduler, percentiles, simulate
+from paper_1810_01609_amd.serve import Request, Scheduler, merge_chunks, percentiles, simulate, split_requests
 
 GBS = 4000e9  # modelled sustained bandwidth
 
@@ -106,3 +106,14 @@ def test_slot_cap_per_lane():
     tr = [Request(i, 0.0, V, 8, 0.01, 12) for i in range(4)]
     simulate(tr, be, 1 << 40, max_slots_per_lane=24)
     assert be.max_slots_seen[(V, 8)] <= 24
+
+
+def test_split_and_merge_chunks():
+    tr = [Request(7, 0.5, (8, 8, 8, 16), 8, 0.01, 12, seed=3), Request(8, 0.6, (8, 8, 8, 16), 8, 0.01, 2)]
+    parts = split_requests(tr, 5)
+    assert [(p.id, p.nsrc, p.src_offset, p.parent) for p in parts] == [
+        (7000, 5, 0, 7), (7001, 5, 5, 7), (7002, 2, 10, 7), (8, 2, 0, -1)]
+    sched = simulate(parts, FakeBackend(), 1 << 40)
+    merged = {r.id: r for r in merge_chunks(sched.done)}
+    assert merged[7].nsrc == 12 and merged[8].nsrc == 2
+    assert merged[7].t_done == max(r.t_done for r in sched.done if r.parent == 7)
