@@ -227,17 +227,28 @@ static std::string tune_key(const Geom& g, int prec, const Prog& p, int nslots, 
   return buf;
 }
 
-static void candidates(const Geom& g, int prec, const DslashArgs& A, std::vector<int>& out, int& dflt) {
+// Launch candidates: log2 of sites per workgroup (bits 0-7) and LDS staging
+// of links / neighbour indices (bit 8).
+static int default_stage() {
+  const char* e = getenv("MDWF_STAGE");
+  return (e != nullptr && e[0] == '0') ? 0 : 1;
+}
+
+static void candidates(const Geom& g, int prec, DslashArgs A, bool hop, std::vector<int>& out, int& dflt) {
   out.clear();
   dflt = -1;
-  for (int lg = 4; lg <= 7; ++lg) {
-    const int CB = 1 << lg;
-    if (CB * g.L5 > dslash_max_threads(prec)) break;
-    if (CB > 2 * g.Vh && lg > 4) break;
-    const size_t lds = dslash_lds_bytes(A, prec, lg);
-    if (lds > 160 * 1024) break;
-    out.push_back(lg);
-    if (lds <= 64 * 1024 && CB <= 64) dflt = lg;
+  const int want_stage = hop ? default_stage() : 0;
+  for (int stage = 0; stage <= (hop ? 1 : 0); ++stage) {
+    A.stage = stage;
+    for (int lg = 4; lg <= 7; ++lg) {
+      const int CB = 1 << lg;
+      if (CB * g.L5 > dslash_max_threads(prec)) break;
+      if (CB > 2 * g.Vh && lg > 4) break;
+      const size_t lds = dslash_lds_bytes(A, prec, lg, hop);
+      if (lds > 160 * 1024) break;
+      out.push_back(lg | (stage << 8));
+      if (stage == want_stage && lds <= 64 * 1024 && CB <= 64) dflt = lg | (stage << 8);
+    }
   }
   if (dflt < 0 && !out.empty()) dflt = out.front();
 }
@@ -284,7 +295,7 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int pre
   }
   std::vector<int> cand;
   int dflt = 4;
-  candidates(geom, prec, A, cand, dflt);
+  candidates(geom, prec, A, pr.hop, cand, dflt);
   if (cand.empty()) return hipErrorInvalidValue;
   int lg = dflt;
   const std::string key = tune_key(geom, prec, pr, nslots, fuse != nullptr);
@@ -300,13 +311,14 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int pre
     float best = 1e30f;
     int best_lg = dflt;
     for (int cl : cand) {
-      hipError_t e = dslash_launch(A, prec, pr.hop, pr.dag, pr.pro, cl, c->stream);  // warm-up
+      A.stage = cl >> 8;
+      hipError_t e = dslash_launch(A, prec, pr.hop, pr.dag, pr.pro, cl & 0xff, c->stream);  // warm-up
       if (e != hipSuccess) {
         (void)hipGetLastError();
         continue;
       }
       (void)hipEventRecord(e0, c->stream);
-      for (int r = 0; r < 3; ++r) (void)dslash_launch(A, prec, pr.hop, pr.dag, pr.pro, cl, c->stream);
+      for (int r = 0; r < 3; ++r) (void)dslash_launch(A, prec, pr.hop, pr.dag, pr.pro, cl & 0xff, c->stream);
       (void)hipEventRecord(e1, c->stream);
       (void)hipEventSynchronize(e1);
       float ms = 0;
@@ -324,7 +336,8 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int pre
   }
   hipEvent_t ev;
   prof_begin(c, &ev);
-  hipError_t e = dslash_launch(A, prec, pr.hop, pr.dag, pr.pro, lg, c->stream);
+  A.stage = lg >> 8;
+  hipError_t e = dslash_launch(A, prec, pr.hop, pr.dag, pr.pro, lg & 0xff, c->stream);
   prof_end(c, cls, prog_bytes(geom, prec, pr, nslots, fuse != nullptr), ev);
   return e;
 }
@@ -605,7 +618,7 @@ mdwf_status mdwf_tune_load(mdwf_ctx* c, const char* path) {
     int lg = -1;
     float ms = 0;
     rest >> lg >> ms;
-    if (lg >= 4 && lg <= 7) {
+    if ((lg & 0xff) >= 4 && (lg & 0xff) <= 7 && (lg >> 8) <= 1) {
       c->tune[line.substr(0, bar)] = lg;
       c->tune_ms[line.substr(0, bar)] = ms;
     }

@@ -281,10 +281,26 @@ template <class R> __device__ __forceinline__ void reconstruct_row2(Cplx<R> U[3]
   U[2][2] = {a.re - b.re, -(a.im - b.im)};
 }
 
+// U from its 12 stored reals r = (row 0, row 1) as (re, im) pairs
+template <class R> __device__ __forceinline__ void link_from_raw(const R r[12], Cplx<R> U[3][3]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) U[k / 3][k % 3] = {r[2 * k], r[2 * k + 1]};
+  reconstruct_row2(U);
+}
+
 template <int P> struct LinkIO;
 
 template <> struct LinkIO<F64> {
   using R = double;
+  static __device__ __forceinline__ void load_raw(const char* gbase, int Vh, int par, int mu, int cb, R r[12]) {
+    const double2* p = reinterpret_cast<const double2*>(gbase) + (size_t)((par * 4 + mu) * 6) * Vh + cb;
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+      const v2d d = ldg<v2d>(p + (size_t)g * Vh);
+      r[2 * g] = d.x;
+      r[2 * g + 1] = d.y;
+    }
+  }
   static __device__ __forceinline__ void load(const char* gbase, int Vh, int par, int mu, int cb, Cplx<R> U[3][3]) {
     const double2* p = reinterpret_cast<const double2*>(gbase) + (size_t)((par * 4 + mu) * 6) * Vh + cb;
 #pragma unroll
@@ -298,6 +314,14 @@ template <> struct LinkIO<F64> {
 
 template <> struct LinkIO<F32> {
   using R = float;
+  static __device__ __forceinline__ void load_raw(const char* gbase, int Vh, int par, int mu, int cb, R r[12]) {
+    const float4* p = reinterpret_cast<const float4*>(gbase) + (size_t)((par * 4 + mu) * 3) * Vh + cb;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      const v4f d = ldg<v4f>(p + (size_t)g * Vh);
+      r[4 * g] = d.x; r[4 * g + 1] = d.y; r[4 * g + 2] = d.z; r[4 * g + 3] = d.w;
+    }
+  }
   static __device__ __forceinline__ void load(const char* gbase, int Vh, int par, int mu, int cb, Cplx<R> U[3][3]) {
     const float4* p = reinterpret_cast<const float4*>(gbase) + (size_t)((par * 4 + mu) * 3) * Vh + cb;
     float r[12];
@@ -314,6 +338,15 @@ template <> struct LinkIO<F32> {
 
 template <int P> struct LinkIO16 {
   using R = float;
+  static __device__ __forceinline__ void load_raw(const char* gbase, int Vh, int par, int mu, int cb, R r[12]) {
+    const uint2* p = reinterpret_cast<const uint2*>(gbase) + (size_t)((par * 4 + mu) * 3) * Vh + cb;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      const v2u d = ldg<v2u>(p + (size_t)g * Vh);
+      unpack2<P>(d.x, r[4 * g], r[4 * g + 1]);
+      unpack2<P>(d.y, r[4 * g + 2], r[4 * g + 3]);
+    }
+  }
   static __device__ __forceinline__ void load(const char* gbase, int Vh, int par, int mu, int cb, Cplx<R> U[3][3]) {
     const uint2* p = reinterpret_cast<const uint2*>(gbase) + (size_t)((par * 4 + mu) * 3) * Vh + cb;
     float r[12];

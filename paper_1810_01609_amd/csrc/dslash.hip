@@ -128,9 +128,57 @@ __device__ __forceinline__ void pin_acc(Cplx<R> acc[4][3]) {
                  "+v"(acc[a][2].re), "+v"(acc[a][2].im) : : "memory");
 }
 
-template <int P, bool DAG, bool PRO, int MU>
+// Per-workgroup staging of the stencil's geometry and links in LDS: for each
+// of the CB sites and 8 directions (mu forward 0..3, backward 4..7) the
+// neighbour's index (bit 31 = crosses the antiperiodic t boundary) and the
+// link's 12 reals, loaded once and shared by the site's L5 slice threads.
+template <class R> struct Stage {
+  int* nbr;  // [8][CB]
+  R* lnk;    // [8*12][CB]
+};
+
+template <int P>
+__device__ __forceinline__ void stage_fill(const DslashArgs& A, Stage<typename PrecTraits<P>::Real> st, int CB,
+                                           int cb_log2, int sblk, int tid, int nthr) {
+  using R = typename PrecTraits<P>::Real;
+  const Geom& g = A.g;
+  for (int task = tid; task < CB * 8; task += nthr) {
+    const int cbl = task & (CB - 1);
+    const int dir = task >> cb_log2;
+    const int cb = sblk * CB + cbl;
+    int nb = 0;
+    R r[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) r[k] = 0;
+    if (cb < g.Vh) {
+      int X[4];
+      site_coords(g, A.out_par, cb, X[0], X[1], X[2], X[3]);
+      const int mu = dir & 3;
+      const int Lmu = mu == 0 ? g.Lx : mu == 1 ? g.Ly : mu == 2 ? g.Lz : g.Lt;
+      bool flip;
+      if (dir < 4) {
+        flip = mu == 3 && g.tap && X[3] == g.Lt - 1;
+        X[mu] = X[mu] + 1 == Lmu ? 0 : X[mu] + 1;
+        nb = cb_index(g, X[0], X[1], X[2], X[3]);
+        LinkIO<P>::load_raw(A.gauge, g.Vh, A.out_par, mu, cb, r);
+      } else {
+        flip = mu == 3 && g.tap && X[3] == 0;
+        X[mu] = X[mu] == 0 ? Lmu - 1 : X[mu] - 1;
+        nb = cb_index(g, X[0], X[1], X[2], X[3]);
+        LinkIO<P>::load_raw(A.gauge, g.Vh, 1 - A.out_par, mu, nb, r);
+      }
+      if (flip) nb |= (int)0x80000000u;
+    }
+    st.nbr[dir * CB + cbl] = nb;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) st.lnk[(dir * 12 + k) * CB + cbl] = r[k];
+  }
+}
+
+template <int P, bool DAG, bool PRO, bool STAGE, int MU>
 __device__ __forceinline__ void hop_dir(const DslashArgs& A, const FieldDesc& f, const char* in, int cb, int s,
-                               const int X[4], const Coef5& c, Cplx<typename PrecTraits<P>::Real> acc[4][3]) {
+                                        const int X[4], const Coef5& c, Cplx<typename PrecTraits<P>::Real> acc[4][3],
+                                        Stage<typename PrecTraits<P>::Real> st, int CB, int cbl) {
   using R = typename PrecTraits<P>::Real;
   const Geom& g = A.g;
   const int Lmu = MU == 0 ? g.Lx : MU == 1 ? g.Ly : MU == 2 ? g.Lz : g.Lt;
@@ -138,48 +186,53 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& A, const FieldDesc& f,
   constexpr int SB = -SF;            // backward projector
   Cplx<R> U[3][3], psi[4][3], h[2][3], w[2][3];
   R v[24];
-  // ---- forward: (1 -+ g) U_mu(x) psi(x + mu)
-  {
-    int Y[4] = {X[0], X[1], X[2], X[3]};
-    Y[MU] = X[MU] + 1 == Lmu ? 0 : X[MU] + 1;
-    const int nb = cb_index(g, Y[0], Y[1], Y[2], Y[3]);
+#pragma unroll
+  for (int fb = 0; fb < 2; ++fb) {
+    // fb = 0 forward: (1 -+ g) U_mu(x) psi(x + mu); fb = 1 backward: (1 +- g) U_mu(x - mu)^dag psi(x - mu)
+    int nb;
+    bool flip;
+    if constexpr (STAGE) {
+      const int e = st.nbr[(MU + 4 * fb) * CB + cbl];
+      nb = e & 0x7fffffff;
+      flip = e < 0;
+      R r[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) r[k] = st.lnk[((MU + 4 * fb) * 12 + k) * CB + cbl];
+      link_from_raw(r, U);
+    } else {
+      int Y[4] = {X[0], X[1], X[2], X[3]};
+      if (fb == 0) {
+        Y[MU] = X[MU] + 1 == Lmu ? 0 : X[MU] + 1;
+        flip = MU == 3 && g.tap && X[3] == g.Lt - 1;
+      } else {
+        Y[MU] = X[MU] == 0 ? Lmu - 1 : X[MU] - 1;
+        flip = MU == 3 && g.tap && X[3] == 0;
+      }
+      nb = cb_index(g, Y[0], Y[1], Y[2], Y[3]);
+      if (fb == 0) LinkIO<P>::load(A.gauge, g.Vh, A.out_par, MU, cb, U);
+      else LinkIO<P>::load(A.gauge, g.Vh, 1 - A.out_par, MU, nb, U);
+    }
     if constexpr (PRO) load_bidiag<P>(in, f, nb, s, g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v);
     else SpinorIO<P>::load(in, f, nb, s, v);
 #pragma unroll
     for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = {v[2 * k], v[2 * k + 1]};
-    LinkIO<P>::load(A.gauge, g.Vh, A.out_par, MU, cb, U);
-    project<MU, SF>(psi, h);
-    if (MU == 3 && g.tap && X[3] == g.Lt - 1) {
+    if (fb == 0) project<MU, SF>(psi, h);
+    else project<MU, SB>(psi, h);
+    if (flip) {
 #pragma unroll
       for (int k = 0; k < 2; ++k)
 #pragma unroll
         for (int a = 0; a < 3; ++a) h[k][a] = {-h[k][a].re, -h[k][a].im};
     }
-    colour_mul<false>(U, h, w);
-    accumulate<MU, SF>(acc, w);
-  }
-  pin_acc(acc);
-  // ---- backward: (1 +- g) U_mu(x - mu)^dag psi(x - mu)
-  {
-    int Y[4] = {X[0], X[1], X[2], X[3]};
-    Y[MU] = X[MU] == 0 ? Lmu - 1 : X[MU] - 1;
-    const int nb = cb_index(g, Y[0], Y[1], Y[2], Y[3]);
-    if constexpr (PRO) load_bidiag<P>(in, f, nb, s, g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v);
-    else SpinorIO<P>::load(in, f, nb, s, v);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = {v[2 * k], v[2 * k + 1]};
-    LinkIO<P>::load(A.gauge, g.Vh, 1 - A.out_par, MU, nb, U);
-    project<MU, SB>(psi, h);
-    if (MU == 3 && g.tap && X[3] == 0) {
-#pragma unroll
-      for (int k = 0; k < 2; ++k)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) h[k][a] = {-h[k][a].re, -h[k][a].im};
+    if (fb == 0) {
+      colour_mul<false>(U, h, w);
+      accumulate<MU, SF>(acc, w);
+    } else {
+      colour_mul<true>(U, h, w);
+      accumulate<MU, SB>(acc, w);
     }
-    colour_mul<true>(U, h, w);
-    accumulate<MU, SB>(acc, w);
+    pin_acc(acc);
   }
-  pin_acc(acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -280,7 +333,7 @@ template <class R> __device__ __forceinline__ void lds_get(const R* lds, int CB,
 // arithmetic variants fit 128 (4 waves per SIMD).
 template <int P> constexpr int kMaxThreads = P == F64 ? 512 : 1024;
 
-template <int P, bool HOP, bool DAG, bool PRO>
+template <int P, bool HOP, bool DAG, bool PRO, bool STAGE>
 __global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
   using R = typename PrecTraits<P>::Real;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -300,23 +353,30 @@ __global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
   const FieldDesc f{A.g.Vh, A.g.L5};
   const int L5 = A.g.L5;
 
+  Stage<R> st{reinterpret_cast<int*>(smem + A.lds_stage_off),
+              reinterpret_cast<R*>(smem + A.lds_stage_off + (size_t)8 * CB * sizeof(int))};
+  if constexpr (HOP && STAGE) {
+    stage_fill<P>(A, st, CB, A.cb_log2, sblk, tid, nthr);
+    __syncthreads();
+  }
+
   R v[24];
 #pragma unroll
   for (int k = 0; k < 24; ++k) v[k] = 0;
   if (valid) {
     if constexpr (HOP) {
-      int X[4];
-      site_coords(A.g, A.out_par, cb, X[0], X[1], X[2], X[3]);
+      int X[4] = {0, 0, 0, 0};
+      if constexpr (!STAGE) site_coords(A.g, A.out_par, cb, X[0], X[1], X[2], X[3]);
       Cplx<R> acc[4][3];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) acc[a][b] = {0, 0};
       const char* in = A.in[slot];
-      hop_dir<P, DAG, PRO, 0>(A, f, in, cb, s, X, c, acc);
-      hop_dir<P, DAG, PRO, 1>(A, f, in, cb, s, X, c, acc);
-      hop_dir<P, DAG, PRO, 2>(A, f, in, cb, s, X, c, acc);
-      hop_dir<P, DAG, PRO, 3>(A, f, in, cb, s, X, c, acc);
+      hop_dir<P, DAG, PRO, STAGE, 0>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+      hop_dir<P, DAG, PRO, STAGE, 1>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+      hop_dir<P, DAG, PRO, STAGE, 2>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+      hop_dir<P, DAG, PRO, STAGE, 3>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
         v[2 * k] = acc[k / 3][k % 3].re;
@@ -405,9 +465,9 @@ __global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
 // ---------------------------------------------------------------------------
 // launcher
 // ---------------------------------------------------------------------------
-template <int P, bool HOP, bool DAG, bool PRO>
+template <int P, bool HOP, bool DAG, bool PRO, bool STAGE>
 static hipError_t launch_t(const DslashArgs& A, int threads, size_t smem, int grid, hipStream_t st) {
-  auto k = dslash5_kernel<P, HOP, DAG, PRO>;
+  auto k = dslash5_kernel<P, HOP, DAG, PRO, STAGE>;
   if (smem > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
@@ -417,33 +477,49 @@ static hipError_t launch_t(const DslashArgs& A, int threads, size_t smem, int gr
   return hipGetLastError();
 }
 
+template <int P, bool STAGE>
+static hipError_t launch_s(const DslashArgs& A, bool dag, bool pro, int threads, size_t smem, int grid,
+                           hipStream_t st) {
+  if (dag) return launch_t<P, true, true, false, STAGE>(A, threads, smem, grid, st);
+  if (pro) return launch_t<P, true, false, true, STAGE>(A, threads, smem, grid, st);
+  return launch_t<P, true, false, false, STAGE>(A, threads, smem, grid, st);
+}
+
 template <int P>
 static hipError_t launch_p(const DslashArgs& A, bool hop, bool dag, bool pro, int threads, size_t smem, int grid,
                            hipStream_t st) {
-  if (!hop) return launch_t<P, false, false, false>(A, threads, smem, grid, st);
-  if (dag) return launch_t<P, true, true, false>(A, threads, smem, grid, st);
-  if (pro) return launch_t<P, true, false, true>(A, threads, smem, grid, st);
-  return launch_t<P, true, false, false>(A, threads, smem, grid, st);
+  if (!hop) return launch_t<P, false, false, false, false>(A, threads, smem, grid, st);
+  if (A.stage) return launch_s<P, true>(A, dag, pro, threads, smem, grid, st);
+  return launch_s<P, false>(A, dag, pro, threads, smem, grid, st);
 }
 
 int dslash_max_threads(int prec) { return prec == F64 ? kMaxThreads<F64> : kMaxThreads<F32>; }
 
-size_t dslash_lds_bytes(const DslashArgs& A, int prec, int cb_log2) {
+// LDS: [fifth-dimension chain columns][reduction][stage: neighbours + links]
+static void lds_layout(const DslashArgs& A, int prec, int cb_log2, bool hop, size_t& chain, size_t& red,
+                       size_t& stage) {
   const size_t CB = (size_t)1 << cb_log2;
   const size_t rb = prec == F64 ? 8 : 4;
-  size_t chain = (A.c1 != CH_NONE || A.c2 != CH_NONE) ? CB * A.g.L5 * 24 * rb : 0;
-  chain = round_up(chain, 16);
-  const size_t red = A.reduce ? CB * A.g.L5 * 8 : 0;
-  return chain + red;
+  chain = (A.c1 != CH_NONE || A.c2 != CH_NONE) ? round_up(CB * A.g.L5 * 24 * rb, 16) : 0;
+  red = A.reduce ? round_up(CB * A.g.L5 * 8, 16) : 0;
+  stage = (hop && A.stage) ? round_up(CB * 8 * 4, 16) + CB * 8 * 12 * rb : 0;
+}
+
+size_t dslash_lds_bytes(const DslashArgs& A, int prec, int cb_log2, bool hop) {
+  size_t chain, red, stage;
+  lds_layout(A, prec, cb_log2, hop, chain, red, stage);
+  return chain + red + stage;
 }
 
 hipError_t dslash_launch(DslashArgs A, int prec, bool hop, bool dag, bool pro, int cb_log2, hipStream_t st) {
   const int CB = 1 << cb_log2;
   A.cb_log2 = cb_log2;
   A.nblk = (A.g.Vh + CB - 1) / CB;
-  size_t chain = (A.c1 != CH_NONE || A.c2 != CH_NONE) ? (size_t)CB * A.g.L5 * 24 * (prec == F64 ? 8 : 4) : 0;
-  A.lds_chain_bytes = (int)round_up(chain, 16);
-  const size_t smem = dslash_lds_bytes(A, prec, cb_log2);
+  size_t chain, red, stage;
+  lds_layout(A, prec, cb_log2, hop, chain, red, stage);
+  A.lds_chain_bytes = (int)chain;
+  A.lds_stage_off = (int)(chain + red);
+  const size_t smem = chain + red + stage;
   const int threads = CB * A.g.L5;
   const long long blocks = (long long)A.nblk * A.nslots;
   const int grid = (int)round_up((size_t)blocks, 8);

@@ -48,6 +48,8 @@ struct DslashArgs {
   int nblk;                // filled by the launcher
   int cb_log2;             // filled by the launcher
   int lds_chain_bytes;     // filled by the launcher
+  int lds_stage_off;       // filled by the launcher
+  int stage;               // 1: stage neighbour indices and links in LDS once per workgroup
   int c1, c2, aux_mode, reduce;
   double coef_y;
   // CG update fused into the epilogue (cg_update = 1): with q the combined
@@ -61,7 +63,7 @@ struct DslashArgs {
 };
 
 hipError_t dslash_launch(DslashArgs A, int prec, bool hop, bool dag, bool pro, int cb_log2, hipStream_t st);
-size_t dslash_lds_bytes(const DslashArgs& A, int prec, int cb_log2);
+size_t dslash_lds_bytes(const DslashArgs& A, int prec, int cb_log2, bool hop);
 int dslash_max_threads(int prec);
 
 // ---- BLAS-1 / reductions (one thread per 4D site, loop over s) ------------
