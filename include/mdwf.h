@@ -75,7 +75,11 @@ typedef enum {
   MDWF_EBUSY = -7       /* resource limit (e.g. job jobs/slots per step)       */
 } mdwf_status;
 
-typedef enum { MDWF_F64 = 0, MDWF_F32 = 1, MDWF_F16 = 2, MDWF_BF16 = 3 } mdwf_prec;
+/* Storage precisions.  F16 / BF16 / I16 store spinors as 16-bit values with
+ * one FP32 scale per 5D site (max |component|; I16 is the paper's fixed-point
+ * "half": value = int16 / 32767 * scale) and links as 16-bit values (I16:
+ * int16 / 32767); their arithmetic is FP32. */
+typedef enum { MDWF_F64 = 0, MDWF_F32 = 1, MDWF_F16 = 2, MDWF_BF16 = 3, MDWF_I16 = 4 } mdwf_prec;
 
 /* Operators for mdwf_dslash.  Half-field operators read the parity they act
  * on from `in` and write the parity they produce into `out`; the other
@@ -109,8 +113,8 @@ typedef struct {
 
 /* CG options.  tol is the relative residual of the normal equations,
  * |b - A x| <= tol |b|, decided on the FP64 residual.  inner is the storage
- * precision of the inner iteration (F64: plain FP64 CG; F32: FP32; F16/BF16:
- * 16-bit storage with a per-site FP32 scale and FP32 arithmetic); every
+ * precision of the inner iteration (F64: plain FP64 CG; F32: FP32; F16/BF16/
+ * I16: 16-bit storage with a per-site FP32 scale and FP32 arithmetic); every
  * reliable update recomputes the FP64 residual when |r| < delta * max|r|
  * since the previous update.  check_every: iterations between host polls. */
 typedef struct {

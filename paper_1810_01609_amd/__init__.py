@@ -7,7 +7,7 @@ serving loop (``serve``).
 """
 from . import mdwf  # noqa: F401
 from .mdwf import (  # noqa: F401
-    Action, CGOpts, Context, MDWFError, F64, F32, F16, BF16, PREC,
+    Action, CGOpts, Context, MDWFError, F64, F32, F16, BF16, I16, PREC,
 )
 
-__all__ = ["mdwf", "Action", "CGOpts", "Context", "MDWFError", "F64", "F32", "F16", "BF16", "PREC"]
+__all__ = ["mdwf", "Action", "CGOpts", "Context", "MDWFError", "F64", "F32", "F16", "BF16", "I16", "PREC"]

@@ -168,6 +168,7 @@ hipError_t blas_cg_xr(BlasArgs A, int px, int ps, hipStream_t st) {
   else if (px == F32 && ps == F32) hipLaunchKernelGGL((k_cg_xr<F32, F32>), grid, blk, 0, st, A);
   else if (px == F32 && ps == F16) hipLaunchKernelGGL((k_cg_xr<F32, F16>), grid, blk, 0, st, A);
   else if (px == F32 && ps == BF16) hipLaunchKernelGGL((k_cg_xr<F32, BF16>), grid, blk, 0, st, A);
+  else if (px == F32 && ps == I16) hipLaunchKernelGGL((k_cg_xr<F32, I16>), grid, blk, 0, st, A);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -180,6 +181,7 @@ hipError_t blas_cg_p(BlasArgs A, int ps, hipStream_t st) {
     case F32: hipLaunchKernelGGL(k_cg_p<F32>, grid, blk, 0, st, A); break;
     case F16: hipLaunchKernelGGL(k_cg_p<F16>, grid, blk, 0, st, A); break;
     case BF16: hipLaunchKernelGGL(k_cg_p<BF16>, grid, blk, 0, st, A); break;
+    case I16: hipLaunchKernelGGL(k_cg_p<I16>, grid, blk, 0, st, A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -193,6 +195,7 @@ static hipError_t axpby_out(BlasArgs A, int pout, dim3 grid, hipStream_t st) {
     case F32: hipLaunchKernelGGL((k_axpby<PI, F32>), grid, blk, 0, st, A); break;
     case F16: hipLaunchKernelGGL((k_axpby<PI, F16>), grid, blk, 0, st, A); break;
     case BF16: hipLaunchKernelGGL((k_axpby<PI, BF16>), grid, blk, 0, st, A); break;
+    case I16: hipLaunchKernelGGL((k_axpby<PI, I16>), grid, blk, 0, st, A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -205,6 +208,7 @@ hipError_t blas_axpby(BlasArgs A, int pin, int pout, hipStream_t st) {
     case F32: return axpby_out<F32>(A, pout, grid, st);
     case F16: return axpby_out<F16>(A, pout, grid, st);
     case BF16: return axpby_out<BF16>(A, pout, grid, st);
+    case I16: return axpby_out<I16>(A, pout, grid, st);
   }
   return hipErrorInvalidValue;
 }
@@ -217,6 +221,7 @@ hipError_t blas_norm_diff(BlasArgs A, int p, hipStream_t st) {
     case F32: hipLaunchKernelGGL(k_norm_diff<F32>, grid, blk, 0, st, A); break;
     case F16: hipLaunchKernelGGL(k_norm_diff<F16>, grid, blk, 0, st, A); break;
     case BF16: hipLaunchKernelGGL(k_norm_diff<BF16>, grid, blk, 0, st, A); break;
+    case I16: hipLaunchKernelGGL(k_norm_diff<I16>, grid, blk, 0, st, A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

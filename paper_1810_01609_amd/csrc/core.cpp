@@ -445,7 +445,7 @@ mdwf_status mdwf_gauge_load(mdwf_ctx* c, const int32_t L[4], const void* links, 
   a.mq = 0;
   std::string msg;
   if (check_action_msg(&a, msg) != MDWF_OK) return set_err(c, MDWF_EINVAL, "mdwf_gauge_load: %s", msg.c_str());
-  if (prec_mask & ~0xfu) return set_err(c, MDWF_EINVAL, "mdwf_gauge_load: prec_mask has unknown bits");
+  if (prec_mask & ~0x1fu) return set_err(c, MDWF_EINVAL, "mdwf_gauge_load: prec_mask has unknown bits");
   prec_mask |= 1u << MDWF_F64;
   (void)hipSetDevice(c->device);
   const Geom g = make_geom(&a);
@@ -473,7 +473,7 @@ mdwf_status mdwf_gauge_load(mdwf_ctx* c, const int32_t L[4], const void* links, 
     dev_links = static_cast<const double*>(staging);
   }
   mdwf_status st = MDWF_OK;
-  for (int p = 0; p < 4 && st == MDWF_OK; ++p) {
+  for (int p = 0; p < 5 && st == MDWF_OK; ++p) {
     if (!(prec_mask & (1u << p))) continue;
     const size_t nb = gauge_field_bytes(p, g.Vh);
     e = hipMalloc(&gf->data[p], nb);
@@ -490,7 +490,7 @@ mdwf_status mdwf_gauge_load(mdwf_ctx* c, const int32_t L[4], const void* links, 
   if (st == MDWF_OK && e != hipSuccess) st = hip_err(c, e, "gauge load");
   if (staging != nullptr) (void)hipFree(staging);
   if (st != MDWF_OK) {
-    for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < 5; ++p)
       if (gf->data[p] != nullptr) (void)hipFree(gf->data[p]);
     delete gf;
     return st;
@@ -505,7 +505,7 @@ mdwf_status mdwf_gauge_free(mdwf_gauge* g) {
     (void)hipSetDevice(g->ctx->device);
     (void)hipStreamSynchronize(g->ctx->stream);
   }
-  for (int p = 0; p < 4; ++p)
+  for (int p = 0; p < 5; ++p)
     if (g->data[p] != nullptr) (void)hipFree(g->data[p]);
   delete g;
   return MDWF_OK;

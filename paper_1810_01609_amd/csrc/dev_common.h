@@ -6,10 +6,12 @@
 // of the site divided by 2, which enumerates one parity when Lx is even):
 //   spinor F64 : double2 [s][12 groups][cb]      group g = complex comp g
 //   spinor F32 : float4  [s][6 groups][cb]       group g = comps 2g, 2g+1
-//   spinor F16/BF16 : 16-byte groups of 8 halves [s][3][cb] (comps 4g..4g+3),
-//              then (256-byte aligned) float scale [s][cb]: value = half*scale
+//   spinor F16/BF16/I16 : 16-byte groups of 8 16-bit values [s][3][cb]
+//              (comps 4g..4g+3), then (256-byte aligned) float scale [s][cb]:
+//              value = half*scale, or int16/32767*scale (fixed point)
 //   gauge  : 12 reals (rows 0,1) per link, [parity][mu][group][cb]
-//            F64 6 x double2, F32 3 x float4, F16/BF16 3 x 4 halves (8 bytes)
+//            F64 6 x double2, F32 3 x float4, F16/BF16/I16 3 x 4 x 16 bits (8 bytes);
+//            I16 links are int16/32767 (|U_ij| <= 1 needs no scale)
 // Complex component index comp = spin*3 + colour, reals interleaved re,im.
 #pragma once
 
@@ -19,13 +21,14 @@
 
 namespace mdwf {
 
-enum Prec : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3 };
+enum Prec : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3, I16 = 4 };
 
 template <int P> struct PrecTraits;
 template <> struct PrecTraits<F64> { using Real = double; };
 template <> struct PrecTraits<F32> { using Real = float; };
 template <> struct PrecTraits<F16> { using Real = float; };
 template <> struct PrecTraits<BF16> { using Real = float; };
+template <> struct PrecTraits<I16> { using Real = float; };
 
 __host__ __device__ __forceinline__ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -131,12 +134,23 @@ __device__ __forceinline__ uint32_t float_to_f16(float f) {
   return (uint32_t)__half_as_ushort(__float2half_rn(f));
 }
 
+// 16-bit fixed point on [-1, 1]: q = rint(f * 32767), f = q / 32767
+__device__ __forceinline__ float i16_to_float(uint32_t bits16) {
+  return (float)(int16_t)(uint16_t)bits16 * (1.0f / 32767.0f);
+}
+__device__ __forceinline__ uint32_t float_to_i16(float f) {
+  const float c = fminf(fmaxf(f, -1.0f), 1.0f) * 32767.0f;
+  return (uint32_t)(uint16_t)(int16_t)__float2int_rn(c);
+}
+
 template <int P> __device__ __forceinline__ float h_to_f(uint32_t b) {
   if constexpr (P == F16) return f16_to_float(b);
+  else if constexpr (P == I16) return i16_to_float(b);
   else return bf16_to_float(b);
 }
 template <int P> __device__ __forceinline__ uint32_t f_to_h(float f) {
   if constexpr (P == F16) return float_to_f16(f);
+  else if constexpr (P == I16) return float_to_i16(f);
   else return float_to_bf16(f);
 }
 template <int P> __device__ __forceinline__ void unpack2(uint32_t w, float& a, float& b) {
@@ -266,6 +280,7 @@ template <int P> struct SpinorIO16 {
 };
 template <> struct SpinorIO<F16> : SpinorIO16<F16> {};
 template <> struct SpinorIO<BF16> : SpinorIO16<BF16> {};
+template <> struct SpinorIO<I16> : SpinorIO16<I16> {};
 
 // ---------------------------------------------------------------------------
 // Gauge links: 12 stored reals, row 2 = conj(row0 x row1).
@@ -363,6 +378,7 @@ template <int P> struct LinkIO16 {
 };
 template <> struct LinkIO<F16> : LinkIO16<F16> {};
 template <> struct LinkIO<BF16> : LinkIO16<BF16> {};
+template <> struct LinkIO<I16> : LinkIO16<I16> {};
 
 // ---------------------------------------------------------------------------
 // 5th-dimension coefficients of one right-hand side (built on the host).

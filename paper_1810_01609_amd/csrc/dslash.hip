@@ -333,7 +333,7 @@ template <class R> __device__ __forceinline__ void lds_get(const R* lds, int CB,
 // arithmetic variants fit 128 (4 waves per SIMD).
 template <int P> constexpr int kMaxThreads = P == F64 ? 512 : 1024;
 
-template <int P, bool HOP, bool DAG, bool PRO, bool STAGE>
+template <int P, bool HOP, bool DAG, bool PRO, bool STAGE, bool CGU>
 __global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
   using R = typename PrecTraits<P>::Real;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
     for (int k = 0; k < 24; ++k) v[k] += w[k];
   }
 
-  if (A.cg_update) {
+  if constexpr (CGU) {
     // x += alpha p, r -= alpha q with q = v; v becomes r for the reduction
     constexpr int PX = P == F64 ? F64 : F32;
     if (valid) {
@@ -459,15 +459,15 @@ __global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
     __syncthreads();
     lds_get(lds, CB, cbl, s, v);
   }
-  if (valid && !A.cg_update) SpinorIO<P>::store(A.out[slot], f, cb, s, v);
+  if (valid && !CGU) SpinorIO<P>::store(A.out[slot], f, cb, s, v);
 }
 
 // ---------------------------------------------------------------------------
 // launcher
 // ---------------------------------------------------------------------------
-template <int P, bool HOP, bool DAG, bool PRO, bool STAGE>
+template <int P, bool HOP, bool DAG, bool PRO, bool STAGE, bool CGU = false>
 static hipError_t launch_t(const DslashArgs& A, int threads, size_t smem, int grid, hipStream_t st) {
-  auto k = dslash5_kernel<P, HOP, DAG, PRO, STAGE>;
+  auto k = dslash5_kernel<P, HOP, DAG, PRO, STAGE, CGU>;
   if (smem > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
@@ -480,6 +480,8 @@ static hipError_t launch_t(const DslashArgs& A, int threads, size_t smem, int gr
 template <int P, bool STAGE>
 static hipError_t launch_s(const DslashArgs& A, bool dag, bool pro, int threads, size_t smem, int grid,
                            hipStream_t st) {
+  if (dag && A.cg_update) return launch_t<P, true, true, false, STAGE, true>(A, threads, smem, grid, st);
+  if (A.cg_update) return hipErrorInvalidValue;  // the CG update is fused into M^+ (B2) only
   if (dag) return launch_t<P, true, true, false, STAGE>(A, threads, smem, grid, st);
   if (pro) return launch_t<P, true, false, true, STAGE>(A, threads, smem, grid, st);
   return launch_t<P, true, false, false, STAGE>(A, threads, smem, grid, st);
@@ -488,7 +490,7 @@ static hipError_t launch_s(const DslashArgs& A, bool dag, bool pro, int threads,
 template <int P>
 static hipError_t launch_p(const DslashArgs& A, bool hop, bool dag, bool pro, int threads, size_t smem, int grid,
                            hipStream_t st) {
-  if (!hop) return launch_t<P, false, false, false, false>(A, threads, smem, grid, st);
+  if (!hop) return A.cg_update ? hipErrorInvalidValue : launch_t<P, false, false, false, false>(A, threads, smem, grid, st);
   if (A.stage) return launch_s<P, true>(A, dag, pro, threads, smem, grid, st);
   return launch_s<P, false>(A, dag, pro, threads, smem, grid, st);
 }
@@ -529,6 +531,7 @@ hipError_t dslash_launch(DslashArgs A, int prec, bool hop, bool dag, bool pro, i
     case F32: return launch_p<F32>(A, hop, dag, pro, threads, smem, grid, st);
     case F16: return launch_p<F16>(A, hop, dag, pro, threads, smem, grid, st);
     case BF16: return launch_p<BF16>(A, hop, dag, pro, threads, smem, grid, st);
+    case I16: return launch_p<I16>(A, hop, dag, pro, threads, smem, grid, st);
   }
   return hipErrorInvalidValue;
 }

@@ -73,7 +73,7 @@ struct mdwf_gauge {
   mdwf_ctx* ctx = nullptr;
   int L[4] = {0, 0, 0, 0};
   int Vh = 0;
-  void* data[4] = {nullptr, nullptr, nullptr, nullptr};  // per precision
+  void* data[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // per precision
   size_t bytes = 0;
 };
 

@@ -132,6 +132,7 @@ hipError_t layout_user_to_half(const Geom& g, const char* const* user, char* con
     case F32: hipLaunchKernelGGL(k_user_to_half<F32>, grid, blk, 0, st, g, user, half, par); break;
     case F16: hipLaunchKernelGGL(k_user_to_half<F16>, grid, blk, 0, st, g, user, half, par); break;
     case BF16: hipLaunchKernelGGL(k_user_to_half<BF16>, grid, blk, 0, st, g, user, half, par); break;
+    case I16: hipLaunchKernelGGL(k_user_to_half<I16>, grid, blk, 0, st, g, user, half, par); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -145,6 +146,7 @@ hipError_t layout_half_to_user(const Geom& g, const char* const* half, char* con
     case F32: hipLaunchKernelGGL(k_half_to_user<F32>, grid, blk, 0, st, g, half, user, par); break;
     case F16: hipLaunchKernelGGL(k_half_to_user<F16>, grid, blk, 0, st, g, half, user, par); break;
     case BF16: hipLaunchKernelGGL(k_half_to_user<BF16>, grid, blk, 0, st, g, half, user, par); break;
+    case I16: hipLaunchKernelGGL(k_half_to_user<I16>, grid, blk, 0, st, g, half, user, par); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -157,6 +159,7 @@ hipError_t layout_gauge(const Geom& g, const double* user, char* out, int p, hip
     case F32: hipLaunchKernelGGL(k_gauge<F32>, grid, blk, 0, st, g, user, out); break;
     case F16: hipLaunchKernelGGL(k_gauge<F16>, grid, blk, 0, st, g, user, out); break;
     case BF16: hipLaunchKernelGGL(k_gauge<BF16>, grid, blk, 0, st, g, user, out); break;
+    case I16: hipLaunchKernelGGL(k_gauge<I16>, grid, blk, 0, st, g, user, out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -39,7 +39,7 @@ extern "C" mdwf_status mdwf_dslash(mdwf_ctx* c, const mdwf_gauge* g, const mdwf_
   if (g == nullptr || in == nullptr || out == nullptr) return set_err(c, MDWF_EINVAL, "mdwf_dslash: NULL argument");
   for (int m = 0; m < 4; ++m)
     if (g->L[m] != act->L[m]) return set_err(c, MDWF_EINVAL, "mdwf_dslash: gauge lattice differs from the action's");
-  if (prec < MDWF_F64 || prec > MDWF_BF16) return set_err(c, MDWF_EINVAL, "mdwf_dslash: bad precision");
+  if (prec < MDWF_F64 || prec > MDWF_I16) return set_err(c, MDWF_EINVAL, "mdwf_dslash: bad precision");
   if (g->data[prec] == nullptr)
     return set_err(c, MDWF_EINVAL, "mdwf_dslash: gauge field was not loaded in precision %d", prec);
   if (op < MDWF_OP_D || op > MDWF_OP_PREP) return set_err(c, MDWF_EINVAL, "mdwf_dslash: bad operator %d", op);

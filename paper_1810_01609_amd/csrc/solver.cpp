@@ -5,8 +5,8 @@
 // red-black preconditioned system with a "double-half" CG: most work in
 // 16-bit storage with FP32 arithmetic, with occasional reliable updates to
 // full double precision.  Here:
-//   * the inner iteration runs in FP64, FP32, or FP16/BF16 storage with a
-//     per-site scale (FP32 arithmetic); its solution increment x is FP32
+//   * the inner iteration runs in FP64, FP32, or 16-bit storage (FP16, BF16
+//     or the paper's int16 fixed point) with a per-site scale (FP32 arithmetic); its solution increment x is FP32
 //     (FP64 for the plain solver) and all reductions are FP64;
 //   * a reliable update (Sleijpen & van der Vorst 1996) folds x into the FP64
 //     solution xh and recomputes the FP64 residual rh = M^+(eta^ - M^ xh)
@@ -198,7 +198,7 @@ static mdwf_status check_opts(mdwf_ctx* c, const mdwf_cg_opts* o) {
   if (o == nullptr) return set_err(c, MDWF_EINVAL, "cg options are NULL");
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return set_err(c, MDWF_EINVAL, "tol must be > 0");
   if (o->max_iter < 1) return set_err(c, MDWF_EINVAL, "max_iter must be >= 1");
-  if (o->inner < MDWF_F64 || o->inner > MDWF_BF16) return set_err(c, MDWF_EINVAL, "bad inner precision");
+  if (o->inner < MDWF_F64 || o->inner > MDWF_I16) return set_err(c, MDWF_EINVAL, "bad inner precision");
   if (!(o->delta >= 0.0 && o->delta < 1.0)) return set_err(c, MDWF_EINVAL, "delta must be in [0, 1)");
   if (o->use_initial_guess != 0 && o->use_initial_guess != 1)
     return set_err(c, MDWF_EINVAL, "use_initial_guess must be 0 or 1");
@@ -208,7 +208,7 @@ static mdwf_status check_opts(mdwf_ctx* c, const mdwf_cg_opts* o) {
 extern "C" size_t mdwf_job_footprint(const mdwf_action* act, const mdwf_cg_opts* opts, int32_t nrhs) {
   std::string msg;
   if (check_action_msg(act, msg) != MDWF_OK || opts == nullptr || nrhs < 1) return 0;
-  if (opts->inner < MDWF_F64 || opts->inner > MDWF_BF16) return 0;
+  if (opts->inner < MDWF_F64 || opts->inner > MDWF_I16) return 0;
   const Geom g = make_geom(act);
   const SlotLayout L = slot_layout(g, opts->inner);
   // the job's own block, plus the context's three FP64 temporaries

@@ -20,8 +20,8 @@ OK, EINVAL, ENOMEM, EHIP, ENOCONV, EBREAKDOWN, ENAN, EBUSY = 0, -1, -2, -3, -4, 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOCONV", -5: "EBREAKDOWN",
                 -6: "ENAN", -7: "EBUSY"}
 # precisions
-F64, F32, F16, BF16 = 0, 1, 2, 3
-PREC = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
+F64, F32, F16, BF16, I16 = 0, 1, 2, 3, 4
+PREC = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "i16": I16}
 # operators
 (OP_D, OP_DDAG, OP_MHAT, OP_MHATDAG, OP_NORMAL, OP_HOP_EO, OP_HOP_OE, OP_HOP, OP_HOPDAG, OP_M5,
  OP_M5INV, OP_MPHI, OP_PREP) = range(13)

@@ -15,7 +15,7 @@ from gpu_util import empty_like_dev, log, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-13, "f32": 2e-6, "f16": 8e-3, "bf16": 6e-2}
+TOL = {"f64": 1e-13, "f32": 2e-6, "f16": 8e-3, "bf16": 6e-2, "i16": 1e-3}
 
 
 def _sites(L, L5, n, seed):
@@ -47,7 +47,7 @@ def _cfg(name):
     return c, act, oact, U
 
 
-@pytest.mark.parametrize("name,precs", [("c2", ("f64", "f32", "f16", "bf16")), ("c3", ("f32", "f16", "bf16")),
+@pytest.mark.parametrize("name,precs", [("c2", ("f64", "f32", "f16", "bf16", "i16")), ("c3", ("f32", "f16", "bf16", "i16")),
                                         ("c4", ("f32", "f16"))])
 def test_dirac_sampled_full_size(ctx, name, precs):
     from paper_1810_01609_amd import mdwf as M
@@ -72,7 +72,7 @@ def test_dirac_sampled_full_size(ctx, name, precs):
 
 
 @pytest.mark.parametrize("name,inner,nrhs", [("c2", "f32", 1), ("c2", "f64", 1), ("c3", "f16", 1),
-                                             ("c3", "bf16", 1), ("c4", "f16", 2)])
+                                             ("c3", "bf16", 1), ("c3", "i16", 1), ("c4", "f16", 2)])
 def test_solve_sampled_residual_full_size(ctx, name, inner, nrhs):
     import torch
 

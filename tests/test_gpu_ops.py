@@ -6,8 +6,9 @@ a multiple of 16/32/64), L5 = 1, a large L5, periodic and antiperiodic time,
 the free field, and all four storage precisions.
 
 Tolerances (norm-wise relative error): FP64 1e-13 (rounding of ~1e3 flops per
-output), FP32 2e-6, FP16 8e-3 and BF16 6e-2 (11 and 8 significand bits of
-per-site-scaled storage, rounded again at every stored intermediate).
+output), FP32 2e-6, FP16 8e-3, BF16 6e-2 and int16 fixed point 1e-3 (11, 8
+and 15 significant bits of per-site-scaled storage, rounded again at every
+stored intermediate).
 """
 import numpy as np
 import pytest
@@ -18,7 +19,7 @@ from gpu_util import empty_like_dev, log, make_case, rel, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-13, "f32": 2e-6, "f16": 8e-3, "bf16": 6e-2}
+TOL = {"f64": 1e-13, "f32": 2e-6, "f16": 8e-3, "bf16": 6e-2, "i16": 1e-3}
 
 CASES = {
     # name: (L, L5, mq, eps, seed, t_antiperiodic)
@@ -70,7 +71,7 @@ def _setup(ctx, name):
     L, L5, mq, eps, seed, tap = CASES[name]
     U, act, oact = make_case(L, L5, mq, eps, seed, tap)
     if name not in _gauges:
-        _gauges[name] = ctx.gauge_load(L, U, precs=("f64", "f32", "f16", "bf16"))
+        _gauges[name] = ctx.gauge_load(L, U, precs=("f64", "f32", "f16", "bf16", "i16"))
     return U, act, oact, _gauges[name]
 
 
@@ -96,7 +97,7 @@ def test_op_f64(ctx, name, op):
         assert np.abs(O.parity_mask(oact, 0) * got).max() == 0.0
 
 
-@pytest.mark.parametrize("prec", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("prec", ["f32", "f16", "bf16", "i16"])
 @pytest.mark.parametrize("name", ["c1", "ragged", "aniso_l5_16"])
 @pytest.mark.parametrize("op", ["D", "NORMAL", "HOP", "M5INV", "PREP", "MHATDAG"])
 def test_op_low_precision(ctx, prec, name, op):

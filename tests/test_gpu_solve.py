@@ -30,14 +30,14 @@ _cache = {}
 def _c1(ctx):
     if "c1" not in _cache:
         U, act, oact = make_case((4, 4, 4, 8), 8, 0.05, 0.3, 1)
-        g = ctx.gauge_load(act.lattice, U, precs=("f64", "f32", "f16", "bf16"))
+        g = ctx.gauge_load(act.lattice, U, precs=("f64", "f32", "f16", "bf16", "i16"))
         eta = O.point_source(oact, (0, 0, 0, 0), 0, 0)
         psi_o, info = O.solve(U, eta, oact, tol=1e-12)
         _cache["c1"] = (U, act, oact, g, eta, psi_o, info)
     return _cache["c1"]
 
 
-@pytest.mark.parametrize("inner", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("inner", ["f64", "f32", "f16", "bf16", "i16"])
 def test_c1_solve_matches_oracle(ctx, inner):
     from paper_1810_01609_amd import mdwf as M
 
@@ -95,7 +95,7 @@ def test_multi_rhs_equals_single_bitwise(ctx):
     U, act, oact, g, *_ = _c1(ctx)
     n = 4
     etas = np.stack([O.point_source(oact, (0, 0, 0, 0), s, 1) for s in range(3)] + [O.z2_source(oact, 5)])
-    for inner in ("f64", "f32", "f16"):
+    for inner in ("f64", "f32", "f16", "i16"):
         opts = M.CGOpts.make(tol=1e-10, inner=inner)
         psi = empty_like_dev(etas.shape)
         stats = ctx.solve(g, act, opts, to_dev(etas), psi, nrhs=n)
