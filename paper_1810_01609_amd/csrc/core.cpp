@@ -219,16 +219,21 @@ void prof_end(mdwf_ctx* c, int cls, double bytes, hipEvent_t e0) {
 // tiles, so tuning never changes results.  Launches whose output aliases an
 // input are not tuned (no backup/restore of destroyed data is needed then).
 // ---------------------------------------------------------------------------
+static int default_stage();
+
 static std::string tune_key(const Geom& g, int prec, const Prog& p, int nslots, bool cg) {
   char buf[256];
-  snprintf(buf, sizeof(buf), "dslash5 p%d h%d d%d pr%d c%d.%d a%d r%d u%d L%dx%dx%dx%d L5=%d n%d gfx950", prec,
-           (int)p.hop, (int)p.dag, (int)p.pro, p.c1, p.c2, p.aux, p.reduce, (int)cg, g.Lx, g.Ly, g.Lz, g.Lt, g.L5,
-           nslots);
+  snprintf(buf, sizeof(buf), "dslash5 p%d h%d d%d pr%d c%d.%d a%d r%d u%d s%d L%dx%dx%dx%d L5=%d n%d gfx950",
+           prec, (int)p.hop, (int)p.dag, (int)p.pro, p.c1, p.c2, p.aux, p.reduce, (int)cg,
+           p.hop ? default_stage() : 0, g.Lx, g.Ly, g.Lz, g.Lt, g.L5, nslots);
   return buf;
 }
 
-// Launch candidates: log2 of sites per workgroup (bits 0-7) and LDS staging
-// of links / neighbour indices (bit 8).
+// Launch candidates: log2 of sites per workgroup (bits 0-7); bit 8 carries
+// the LDS staging of links / neighbour indices, which is fixed per process
+// (MDWF_STAGE, default on) and not searched: the staged and unstaged kernels
+// round differently in the last bit (their multiply-adds are contracted
+// differently), and tuning must never change a result.
 static int default_stage() {
   const char* e = getenv("MDWF_STAGE");
   return (e != nullptr && e[0] == '0') ? 0 : 1;
@@ -237,18 +242,16 @@ static int default_stage() {
 static void candidates(const Geom& g, int prec, DslashArgs A, bool hop, std::vector<int>& out, int& dflt) {
   out.clear();
   dflt = -1;
-  const int want_stage = hop ? default_stage() : 0;
-  for (int stage = 0; stage <= (hop ? 1 : 0); ++stage) {
-    A.stage = stage;
-    for (int lg = 4; lg <= 7; ++lg) {
-      const int CB = 1 << lg;
-      if (CB * g.L5 > dslash_max_threads(prec)) break;
-      if (CB > 2 * g.Vh && lg > 4) break;
-      const size_t lds = dslash_lds_bytes(A, prec, lg, hop);
-      if (lds > 160 * 1024) break;
-      out.push_back(lg | (stage << 8));
-      if (stage == want_stage && lds <= 64 * 1024 && CB <= 64) dflt = lg | (stage << 8);
-    }
+  const int stage = hop ? default_stage() : 0;
+  A.stage = stage;
+  for (int lg = 4; lg <= 7; ++lg) {
+    const int CB = 1 << lg;
+    if (CB * g.L5 > dslash_max_threads(prec)) break;
+    if (CB > 2 * g.Vh && lg > 4) break;
+    const size_t lds = dslash_lds_bytes(A, prec, lg, hop);
+    if (lds > 160 * 1024) break;
+    out.push_back(lg | (stage << 8));
+    if (lds <= 64 * 1024 && CB <= 64) dflt = lg | (stage << 8);
   }
   if (dflt < 0 && !out.empty()) dflt = out.front();
 }
