@@ -168,8 +168,21 @@ def dslash_bench(args):
                   "bytes_per_launch": d["bytes"] / d["launches"], "launches": d["launches"]}
     g.free()
     ctx.close()
+    del x, y
+    # achievable HBM bandwidth for context: a plain 4 GiB device copy
+    a = torch.ones(1 << 29, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     print(json.dumps({"workload": args.workload, "lattice": list(L), "L5": L5, "nrhs": nrhs,
-                      "op": "M^+M^ (4 fused stencil launches)", "tuned": bool(args.tune), "dslash": out}),
+                      "op": "M^+M^ (4 fused stencil launches)", "tuned": bool(args.tune), "dslash": out,
+                      "device_copy_GB_per_s": copy_gbs}),
           flush=True)
 
 

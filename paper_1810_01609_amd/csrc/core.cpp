@@ -221,6 +221,20 @@ void prof_end(mdwf_ctx* c, int cls, double bytes, hipEvent_t e0) {
 // ---------------------------------------------------------------------------
 static int default_stage();
 
+// Time slices per traversal block: the largest of 8, 4, 2 dividing Lt whose
+// (Bt + 2) xy-planes of one RHS fit comfortably in a 4 MB XCD L2 (MDWF_BT
+// overrides; 0 = linear order).
+static int traversal_bt(const Geom& g, int prec, int nslots) {
+  const char* e = getenv("MDWF_BT");
+  if (e != nullptr && e[0] != 0) return atoi(e);
+  const double plane_bytes = (double)g.Lxh * g.Ly * g.L5 * spinor_site_bytes(prec);
+  for (int bt : {8, 4, 2}) {
+    if (g.Lt % bt != 0) continue;
+    if ((bt + 2) * plane_bytes * (nslots > 4 ? 4 : nslots) <= 3.0e6) return bt;
+  }
+  return g.Lt % 2 == 0 ? 2 : 0;
+}
+
 static std::string tune_key(const Geom& g, int prec, const Prog& p, int nslots, bool cg) {
   char buf[256];
   snprintf(buf, sizeof(buf), "dslash5 p%d h%d d%d pr%d c%d.%d a%d r%d u%d s%d L%dx%dx%dx%d L5=%d n%d gfx950",
@@ -289,6 +303,7 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int pre
   A.aux_mode = pr.aux;
   A.reduce = pr.reduce;
   A.coef_y = pr.coef;
+  A.order_bt = traversal_bt(geom, prec, nslots);
   if (fuse != nullptr) {
     A.cg_update = 1;
     A.cg_x = fuse->x;

@@ -139,13 +139,13 @@ template <class R> struct Stage {
 
 template <int P>
 __device__ __forceinline__ void stage_fill(const DslashArgs& A, Stage<typename PrecTraits<P>::Real> st, int CB,
-                                           int cb_log2, int sblk, int tid, int nthr) {
+                                           int cb_log2, int cb0, int tid, int nthr) {
   using R = typename PrecTraits<P>::Real;
   const Geom& g = A.g;
   for (int task = tid; task < CB * 8; task += nthr) {
     const int cbl = task & (CB - 1);
     const int dir = task >> cb_log2;
-    const int cb = sblk * CB + cbl;
+    const int cb = cb0 + cbl;
     int nb = 0;
     R r[12];
 #pragma unroll
@@ -176,7 +176,7 @@ __device__ __forceinline__ void stage_fill(const DslashArgs& A, Stage<typename P
 }
 
 template <int P, bool DAG, bool PRO, bool STAGE, int MU>
-__device__ __forceinline__ void hop_dir(const DslashArgs& A, const FieldDesc& f, const char* in, int cb, int s,
+__device__ __forceinline__ void hop_dir_single(const DslashArgs& A, const FieldDesc& f, const char* in, int cb, int s,
                                         const int X[4], const Coef5& c, Cplx<typename PrecTraits<P>::Real> acc[4][3],
                                         Stage<typename PrecTraits<P>::Real> st, int CB, int cbl) {
   using R = typename PrecTraits<P>::Real;
@@ -233,6 +233,69 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& A, const FieldDesc& f,
     }
     pin_acc(acc);
   }
+}
+
+
+// Both neighbours of direction mu (forward and backward) loaded before either
+// is used: two spinor loads in flight per thread instead of one.  Links come
+// from the LDS stage in the compute phase, so only the spinors are buffered.
+template <int P, bool DAG, bool PRO, int MU>
+__device__ __forceinline__ void hop_dir_pair(const DslashArgs& A, const FieldDesc& f, const char* in, int s,
+                                             const Coef5& c, Cplx<typename PrecTraits<P>::Real> acc[4][3],
+                                             Stage<typename PrecTraits<P>::Real> st, int CB, int cbl) {
+  using R = typename PrecTraits<P>::Real;
+  const Geom& g = A.g;
+  constexpr int SF = DAG ? +1 : -1;
+  constexpr int SB = -SF;
+  R v0[24], v1[24];
+  const int e0 = st.nbr[MU * CB + cbl];
+  const int e1 = st.nbr[(MU + 4) * CB + cbl];
+  if constexpr (PRO) {
+    load_bidiag<P>(in, f, e0 & 0x7fffffff, s, g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v0);
+    load_bidiag<P>(in, f, e1 & 0x7fffffff, s, g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v1);
+  } else {
+    SpinorIO<P>::load(in, f, e0 & 0x7fffffff, s, v0);
+    SpinorIO<P>::load(in, f, e1 & 0x7fffffff, s, v1);
+  }
+  Cplx<R> U[3][3], psi[4][3], h[2][3], w[2][3];
+#pragma unroll
+  for (int fb = 0; fb < 2; ++fb) {
+    const R* v = fb == 0 ? v0 : v1;
+    R r[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) r[k] = st.lnk[((MU + 4 * fb) * 12 + k) * CB + cbl];
+    link_from_raw(r, U);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = {v[2 * k], v[2 * k + 1]};
+    if (fb == 0) project<MU, SF>(psi, h);
+    else project<MU, SB>(psi, h);
+    if ((fb == 0 ? e0 : e1) < 0) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) h[k][a] = {-h[k][a].re, -h[k][a].im};
+    }
+    if (fb == 0) {
+      colour_mul<false>(U, h, w);
+      accumulate<MU, SF>(acc, w);
+    } else {
+      colour_mul<true>(U, h, w);
+      accumulate<MU, SB>(acc, w);
+    }
+  }
+  pin_acc(acc);
+}
+
+#ifndef MDWF_HOP_PAIR
+#define MDWF_HOP_PAIR 0
+#endif
+
+template <int P, bool DAG, bool PRO, bool STAGE, int MU>
+__device__ __forceinline__ void hop_dir(const DslashArgs& A, const FieldDesc& f, const char* in, int cb, int s,
+                                        const int X[4], const Coef5& c, Cplx<typename PrecTraits<P>::Real> acc[4][3],
+                                        Stage<typename PrecTraits<P>::Real> st, int CB, int cbl) {
+  if constexpr (STAGE && MDWF_HOP_PAIR) hop_dir_pair<P, DAG, PRO, MU>(A, f, in, s, c, acc, st, CB, cbl);
+  else hop_dir_single<P, DAG, PRO, STAGE, MU>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
 }
 
 // ---------------------------------------------------------------------------
@@ -329,6 +392,28 @@ template <class R> __device__ __forceinline__ void lds_get(const R* lds, int CB,
 // The kernel.  HOP = false turns it into a pure fifth-dimension operator
 // (input and output of the same parity).
 // ---------------------------------------------------------------------------
+// First site of workgroup q.  order_bt = 0: consecutive workgroups take
+// consecutive ranges of cb (t is the slowest index, so a site's t-neighbours
+// are a whole time slice away in the access stream).  order_bt = Bt > 0 (the
+// xy-plane holds a whole number of workgroups, Bt divides Lt): xy-planes are
+// visited in blocks of Bt time slices, z inside a block, t fastest, so the
+// z- and t-neighbour planes of a plane are at most Bt planes away and stay in
+// the XCD's L2.  Sites inside a plane stay consecutive (same reduction tiles).
+__device__ __forceinline__ int block_first_site(const DslashArgs& A, int q, int CB) {
+  if (A.order_bt == 0) return q * CB;
+  const Geom& g = A.g;
+  const int plane = g.Lxh * g.Ly;
+  const int bpp = plane / CB;  // workgroups per plane
+  const int k = q % bpp;
+  int r = q / bpp;
+  const int tt = r % A.order_bt;
+  r /= A.order_bt;
+  const int z = r % g.Lz;
+  const int tb = r / g.Lz;
+  const int t = tb * A.order_bt + tt;
+  return (t * g.Lz + z) * plane + k * CB;
+}
+
 // FP64 needs ~180 VGPRs per thread (2 waves per SIMD), the 32-bit
 // arithmetic variants fit 128 (4 waves per SIMD).
 template <int P> constexpr int kMaxThreads = P == F64 ? 512 : 1024;
@@ -345,9 +430,9 @@ __global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   if (lb >= A.nslots * A.nblk) return;
   const int slot = lb % A.nslots;
-  const int sblk = lb / A.nslots;
+  const int cb0 = block_first_site(A, lb / A.nslots, CB);
   if (A.active != nullptr && A.active[(size_t)slot * A.active_stride] == 0) return;
-  const int cb = sblk * CB + cbl;
+  const int cb = cb0 + cbl;
   const bool valid = cb < A.g.Vh;
   const Coef5 c = A.coef[slot];
   const FieldDesc f{A.g.Vh, A.g.L5};
@@ -356,7 +441,7 @@ __global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
   Stage<R> st{reinterpret_cast<int*>(smem + A.lds_stage_off),
               reinterpret_cast<R*>(smem + A.lds_stage_off + (size_t)8 * CB * sizeof(int))};
   if constexpr (HOP && STAGE) {
-    stage_fill<P>(A, st, CB, A.cb_log2, sblk, tid, nthr);
+    stage_fill<P>(A, st, CB, A.cb_log2, cb0, tid, nthr);
     __syncthreads();
   }
 
@@ -446,7 +531,7 @@ __global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
     site += __shfl_xor(site, 2);
     site += __shfl_xor(site, 1);
     if (s == 0 && (cbl & 15) == 0) {
-      const int tile = (sblk * CB + cbl) >> 4;
+      const int tile = cb >> 4;
       if (tile < A.ntiles) A.partials[(size_t)slot * A.ntiles + tile] = site;
     }
   }
@@ -517,6 +602,8 @@ hipError_t dslash_launch(DslashArgs A, int prec, bool hop, bool dag, bool pro, i
   const int CB = 1 << cb_log2;
   A.cb_log2 = cb_log2;
   A.nblk = (A.g.Vh + CB - 1) / CB;
+  const int plane = A.g.Lxh * A.g.Ly;
+  if (A.order_bt > 0 && (plane % CB != 0 || A.g.Lt % A.order_bt != 0)) A.order_bt = 0;
   size_t chain, red, stage;
   lds_layout(A, prec, cb_log2, hop, chain, red, stage);
   A.lds_chain_bytes = (int)chain;

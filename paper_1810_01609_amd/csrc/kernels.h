@@ -50,6 +50,7 @@ struct DslashArgs {
   int lds_chain_bytes;     // filled by the launcher
   int lds_stage_off;       // filled by the launcher
   int stage;               // 1: stage neighbour indices and links in LDS once per workgroup
+  int order_bt;            // > 0: blocked (z, t) plane traversal with Bt time slices per block
   int c1, c2, aux_mode, reduce;
   double coef_y;
   // CG update fused into the epilogue (cg_update = 1): with q the combined

@@ -13,7 +13,8 @@ import os
 from dataclasses import dataclass
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmdwf.so")
+# MDWF_LIB_PATH selects another build of the library (e.g. a variant being compared)
+LIB_PATH = os.environ.get("MDWF_LIB_PATH") or os.path.join(_HERE, "libmdwf.so")
 
 # status codes
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, EBREAKDOWN, ENAN, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7

@@ -29,6 +29,8 @@ CASES = {
     "l5one": ((4, 2, 2, 4), 1, 0.05, 0.3, 7, 1),
     "aniso_l5_16": ((10, 4, 2, 6), 16, 0.02, 0.2, 8, 1),
     "free": ((4, 4, 2, 4), 4, 0.1, 0.0, 0, 1),
+    # xy-plane of 64 sites per parity: the blocked (z, t) traversal engages
+    "blocked": ((16, 8, 4, 8), 4, 0.05, 0.3, 9, 1),
 }
 
 
