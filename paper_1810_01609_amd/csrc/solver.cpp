@@ -46,7 +46,7 @@ double now_s() {
 int inner_x_prec(int ps) { return ps == F64 ? F64 : F32; }
 
 struct SlotLayout {
-  size_t fs, fx, fxh, total;
+  size_t fs, fx, fxh, feh, total;
 };
 
 SlotLayout slot_layout(const Geom& g, int ps) {
@@ -54,7 +54,8 @@ SlotLayout slot_layout(const Geom& g, int ps) {
   L.fs = round_up(spinor_field_bytes(ps, g.L5, g.Vh), 256);
   L.fx = round_up(spinor_field_bytes(inner_x_prec(ps), g.L5, g.Vh), 256);
   L.fxh = ps == F64 ? 0 : round_up(spinor_field_bytes(F64, g.L5, g.Vh), 256);
-  L.total = 4 * L.fs + L.fx + L.fxh;
+  L.feh = round_up(spinor_field_bytes(F64, g.L5, g.Vh), 256);  // eta^_e, kept for reliable updates
+  L.total = 4 * L.fs + L.fx + L.fxh + L.feh;
   return L;
 }
 
@@ -176,12 +177,9 @@ struct One {
   }
 };
 
-// rh (in T.t1) = M^+ (eta^ - M^ xh), eta^ rebuilt from the user source
-static void true_residual(One& o, const FP64Temps& T, const char* eta_user, const char* xh) {
-  o.to_half(eta_user, T.t1, 0);
-  o.to_half(eta_user, T.t2, 1);
-  o.prog(prog_5D(CH_M5INV), T.t2, nullptr, T.t2);          // M5^-1 eta_o
-  o.prog(prog_PRE(0), T.t2, T.t1, T.t1);                    // eta^_e
+// rh (in T.t1) = M^+ (eta^ - M^ xh), with eta^_e kept by the job
+static void true_residual(One& o, const FP64Temps& T, const char* eta_hat, const char* xh) {
+  o.axpby(eta_hat, F64, T.t1, F64, 1.0, 0.0);               // eta^_e
   o.prog(prog_A1(), xh, nullptr, T.t2);                      // M_phi M5^-1 H_oe M_phi xh
   o.prog(prog_A2(false, false), T.t2, xh, T.t3);             // M^ xh
   o.axpby(T.t3, F64, T.t1, F64, -1.0, 1.0);                  // y = eta^ - M^ xh
@@ -277,7 +275,7 @@ static mdwf_status reliable_update(mdwf_ctx* c, mdwf_job* j, int r, double& rr) 
     o.axpby(j->fx[r], j->px, xh, F64, 1.0, 1.0);
     o.zero(j->fx[r], spinor_field_bytes(j->px, j->geom.L5, j->geom.Vh));
   }
-  true_residual(o, T, j->eta + j->user_bytes * r, xh);
+  true_residual(o, T, j->feh[r], xh);
   o.axpby(T.t1, F64, j->fr[r], j->ps, 1.0, 0.0);
   if (o.e != hipSuccess) return hip_err(c, o.e, "reliable update");
   std::vector<double> n;
@@ -345,6 +343,7 @@ extern "C" mdwf_status mdwf_job_begin(mdwf_ctx* c, const mdwf_gauge* g, const md
     j->fv.push_back(p); p += L.fs;
     j->fx.push_back(p); p += L.fx;
     j->fxh.push_back(L.fxh ? p : nullptr); p += L.fxh;
+    j->feh.push_back(p); p += L.feh;
   }
   j->st.assign(nrhs, CGState{});
   j->stats.assign(nrhs, mdwf_cg_stats{});
@@ -368,6 +367,7 @@ extern "C" mdwf_status mdwf_job_begin(mdwf_ctx* c, const mdwf_gauge* g, const md
     o.to_half(er, T.t2, 1);
     o.prog(prog_5D(CH_M5INV), T.t2, nullptr, T.t2);
     o.prog(prog_PRE(0), T.t2, T.t1, T.t1);
+    o.axpby(T.t1, F64, j->feh[r], F64, 1.0, 0.0);  // keep eta^_e
     o.prog(prog_5D(CH_M5INV_DAG), T.t1, nullptr, T.t3);
     o.prog(prog_B1(), T.t3, nullptr, T.t2);
     o.prog(prog_B2(), T.t2, T.t3, T.t1);
@@ -380,7 +380,7 @@ extern "C" mdwf_status mdwf_job_begin(mdwf_ctx* c, const mdwf_gauge* g, const md
     double rr = bb;
     if (opts->use_initial_guess) {
       o.to_half(j->psi + ub * r, xh, 0);
-      true_residual(o, T, er, xh);
+      true_residual(o, T, j->feh[r], xh);
       if (o.e != hipSuccess) { st = hip_err(c, o.e, "job setup"); break; }
       st = norms_f64(c, geom, a, nullptr, n);
       if (st != MDWF_OK) break;
