@@ -286,6 +286,82 @@ __device__ __forceinline__ void hop_dir_pair(const DslashArgs& A, const FieldDes
   pin_acc(acc);
 }
 
+// Software-pipelined hop over the 8 neighbours (mu forward, mu backward, ...):
+// the spinor of neighbour k+1 is requested before neighbour k is computed, so
+// each thread always has one neighbour load in flight behind its arithmetic.
+// Links and neighbour indices come from the LDS stage.
+template <int P, bool PRO>
+__device__ __forceinline__ void pipe_load(const DslashArgs& A, const FieldDesc& f, const char* in, int s,
+                                          const Coef5& c, int e, typename PrecTraits<P>::Real v[24]) {
+  using R = typename PrecTraits<P>::Real;
+  if constexpr (PRO) load_bidiag<P>(in, f, e & 0x7fffffff, s, A.g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v);
+  else SpinorIO<P>::load(in, f, e & 0x7fffffff, s, v);
+}
+
+template <int P, bool DAG, int K>
+__device__ __forceinline__ void pipe_compute(const typename PrecTraits<P>::Real v[24], int e,
+                                             Cplx<typename PrecTraits<P>::Real> acc[4][3],
+                                             Stage<typename PrecTraits<P>::Real> st, int CB, int cbl) {
+  using R = typename PrecTraits<P>::Real;
+  constexpr int MU = K >> 1;
+  constexpr int FB = K & 1;  // 0 forward, 1 backward
+  constexpr int SF = DAG ? +1 : -1;
+  constexpr int SIG = FB == 0 ? SF : -SF;
+  Cplx<R> U[3][3], psi[4][3], h[2][3], w[2][3];
+  R r[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) r[k] = st.lnk[((MU + 4 * FB) * 12 + k) * CB + cbl];
+  link_from_raw(r, U);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = {v[2 * k], v[2 * k + 1]};
+  project<MU, SIG>(psi, h);
+  if (e < 0) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) h[k][a] = {-h[k][a].re, -h[k][a].im};
+  }
+  colour_mul<FB == 1>(U, h, w);
+  accumulate<MU, SIG>(acc, w);
+}
+
+template <int P, bool DAG, bool PRO, int K>
+__device__ __forceinline__ void pipe_step(const DslashArgs& A, const FieldDesc& f, const char* in, int s,
+                                          const Coef5& c, Cplx<typename PrecTraits<P>::Real> acc[4][3],
+                                          Stage<typename PrecTraits<P>::Real> st, int CB, int cbl,
+                                          typename PrecTraits<P>::Real cur[24], typename PrecTraits<P>::Real nxt[24]) {
+  // neighbour order K = 2*mu + fb; stage index = mu + 4*fb
+  const int e = st.nbr[((K >> 1) + 4 * (K & 1)) * CB + cbl];
+  if constexpr (K < 7) {
+    constexpr int K1 = K + 1;
+    const int e1 = st.nbr[((K1 >> 1) + 4 * (K1 & 1)) * CB + cbl];
+    pipe_load<P, PRO>(A, f, in, s, c, e1, nxt);
+  }
+  pipe_compute<P, DAG, K>(cur, e, acc, st, CB, cbl);
+  pin_acc(acc);
+}
+
+template <int P, bool DAG, bool PRO>
+__device__ __forceinline__ void hop_pipelined(const DslashArgs& A, const FieldDesc& f, const char* in, int s,
+                                              const Coef5& c, Cplx<typename PrecTraits<P>::Real> acc[4][3],
+                                              Stage<typename PrecTraits<P>::Real> st, int CB, int cbl) {
+  using R = typename PrecTraits<P>::Real;
+  R a[24], b[24];
+  pipe_load<P, PRO>(A, f, in, s, c, st.nbr[0 * CB + cbl], a);
+  pipe_step<P, DAG, PRO, 0>(A, f, in, s, c, acc, st, CB, cbl, a, b);
+  pipe_step<P, DAG, PRO, 1>(A, f, in, s, c, acc, st, CB, cbl, b, a);
+  pipe_step<P, DAG, PRO, 2>(A, f, in, s, c, acc, st, CB, cbl, a, b);
+  pipe_step<P, DAG, PRO, 3>(A, f, in, s, c, acc, st, CB, cbl, b, a);
+  pipe_step<P, DAG, PRO, 4>(A, f, in, s, c, acc, st, CB, cbl, a, b);
+  pipe_step<P, DAG, PRO, 5>(A, f, in, s, c, acc, st, CB, cbl, b, a);
+  pipe_step<P, DAG, PRO, 6>(A, f, in, s, c, acc, st, CB, cbl, a, b);
+  pipe_step<P, DAG, PRO, 7>(A, f, in, s, c, acc, st, CB, cbl, b, a);
+}
+
+#ifndef MDWF_HOP_PIPE
+#define MDWF_HOP_PIPE 0
+#endif
+
 #ifndef MDWF_HOP_PAIR
 #define MDWF_HOP_PAIR 0
 #endif
@@ -458,10 +534,14 @@ __global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
 #pragma unroll
         for (int b = 0; b < 3; ++b) acc[a][b] = {0, 0};
       const char* in = A.in[slot];
-      hop_dir<P, DAG, PRO, STAGE, 0>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
-      hop_dir<P, DAG, PRO, STAGE, 1>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
-      hop_dir<P, DAG, PRO, STAGE, 2>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
-      hop_dir<P, DAG, PRO, STAGE, 3>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+      if constexpr (STAGE && MDWF_HOP_PIPE) {
+        hop_pipelined<P, DAG, PRO>(A, f, in, s, c, acc, st, CB, cbl);
+      } else {
+        hop_dir<P, DAG, PRO, STAGE, 0>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+        hop_dir<P, DAG, PRO, STAGE, 1>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+        hop_dir<P, DAG, PRO, STAGE, 2>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+        hop_dir<P, DAG, PRO, STAGE, 3>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+      }
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
         v[2 * k] = acc[k / 3][k % 3].re;
