@@ -145,27 +145,31 @@ def dslash_bench(args):
     ctx = M.Context(0)
     ctx.tune_mode(1 if args.tune else 0)
     U = S.gauge_field(L, cfg["eps"], cfg["seed"])
-    g = ctx.gauge_load(L, U, precs=("f64", "f32", "f16", "bf16"))
+    precs = args.precs.split(",")
+    g = ctx.gauge_load(L, U, precs=tuple(dict.fromkeys(["f64"] + precs)))
     del U
     x = torch.zeros((nrhs,) + act.spinor_shape(), dtype=torch.complex128, device="cuda")
     for r in range(nrhs):
         ctx.source_z2(act, 7, r, x[r])
     y = torch.zeros_like(x)
     out = {}
-    for p in args.precs.split(","):
+    op = {"normal": M.OP_NORMAL, "hop": M.OP_HOP_EO}[args.op]
+    for p in precs:
         cls = M.PROF_DSLASH_F64 if p == "f64" else M.PROF_DSLASH_INNER
         for _ in range(2):
-            ctx.dslash(g, act, M.OP_NORMAL, p, x, y, nrhs=nrhs)
+            ctx.dslash(g, act, op, p, x, y, nrhs=nrhs)
         ctx.profile_enable(True)
         ctx.profile_reset()
         for _ in range(args.steps):
-            ctx.dslash(g, act, M.OP_NORMAL, p, x, y, nrhs=nrhs)
+            ctx.dslash(g, act, op, p, x, y, nrhs=nrhs)
         d = ctx.profile_read(cls)
         ctx.profile_enable(False)
         avg = d["ms"] / d["launches"]
         gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9
         out[p] = {"GB_per_s": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS, "avg_launch_ms": avg,
                   "bytes_per_launch": d["bytes"] / d["launches"], "launches": d["launches"]}
+    if args.tune_save:
+        ctx.tune_save(args.tune_save)
     g.free()
     ctx.close()
     del x, y
@@ -181,7 +185,8 @@ def dslash_bench(args):
     torch.cuda.synchronize()
     copy_gbs = 5 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     print(json.dumps({"workload": args.workload, "lattice": list(L), "L5": L5, "nrhs": nrhs,
-                      "op": "M^+M^ (4 fused stencil launches)", "tuned": bool(args.tune), "dslash": out,
+                      "op": {"normal": "M^+M^ (4 fused stencil launches)", "hop": "H_eo (plain 4D hop)"}[args.op],
+                      "tuned": bool(args.tune), "dslash": out,
                       "device_copy_GB_per_s": copy_gbs}),
           flush=True)
 
@@ -203,8 +208,11 @@ def main():
     ap.add_argument("--hbm-budget-gb", type=float, default=240.0, help="c5: device memory for jobs")
     ap.add_argument("--dslash-only", action="store_true", help="stencil throughput of M^+M^ per precision")
     ap.add_argument("--precs", default="f64,f32,f16,bf16")
+    ap.add_argument("--op", default="normal", choices=("normal", "hop"),
+                    help="dslash-only: the normal operator's four launches, or the plain 4D hop")
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--tune", action="store_true", help="enable the launch autotuner")
+    ap.add_argument("--tune-save", default=None, help="dslash-only: write the tuned launch table here")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (for HBM counter scaling)")
     args = ap.parse_args()

@@ -248,6 +248,19 @@ template <int P> struct SpinorIO16 {
 #pragma unroll
     for (int g = 0; g < 3; ++g) group(base, f, cb, s, g, sc, v + 8 * g);
   }
+  // the 12 stored complex numbers as (re, im) 16-bit pairs, and the site's scale
+  static __device__ __forceinline__ void load_packed(const char* base, const FieldDesc& f, int cb, int s, uint32_t q[12],
+                                                     float& sc) {
+    sc = scale(base, f, cb, s);
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      const v4u d = ldg<v4u>(reinterpret_cast<const uint4*>(base) + ((size_t)s * 3 + g) * f.Vh + cb);
+      q[4 * g] = d.x;
+      q[4 * g + 1] = d.y;
+      q[4 * g + 2] = d.z;
+      q[4 * g + 3] = d.w;
+    }
+  }
   static __device__ __forceinline__ void load_half(const char* base, const FieldDesc& f, int cb, int s, int h, R v[12]) {
     const float sc = scale(base, f, cb, s);
     R t[16];

@@ -15,7 +15,14 @@
 #include "dev_common.h"
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace mdwf {
+
+// One LDS row per site, so a thread's reads are its row base plus immediate
+// offsets; odd row strides keep consecutive sites on distinct banks.
+constexpr int kStageLinkStride = 8 * 18 + 1;  // link reals per site row
+constexpr int kStageNbrStride = 9;            // neighbour indices per site row
 
 // ---------------------------------------------------------------------------
 // spin projection.  h = spins 0,1 of (1 + SIG g_mu) psi; with w = U h the
@@ -30,8 +37,23 @@ template <class R> __device__ __forceinline__ Cplx<R> addi(Cplx<R> a, Cplx<R> b,
   return sg > 0 ? Cplx<R>{a.re - b.im, a.im + b.re} : Cplx<R>{a.re + b.im, a.im - b.re};
 }
 
-template <int MU, int SIG, class R>
-__device__ __forceinline__ void project(const Cplx<R> p[4][3], Cplx<R> h[2][3]) {
+// the same operations on packed 16-bit (re, im) pairs, each result rounded
+// once to the storage format
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ f16x2 add(f16x2 a, f16x2 b) { return a + b; }
+__device__ __forceinline__ f16x2 sub(f16x2 a, f16x2 b) { return a - b; }
+__device__ __forceinline__ f16x2 addi(f16x2 a, f16x2 b, int sg) {
+  return sg > 0 ? a + f16x2{-b.y, b.x} : a + f16x2{b.y, -b.x};
+}
+__device__ __forceinline__ bf16x2 add(bf16x2 a, bf16x2 b) { return a + b; }
+__device__ __forceinline__ bf16x2 sub(bf16x2 a, bf16x2 b) { return a - b; }
+__device__ __forceinline__ bf16x2 addi(bf16x2 a, bf16x2 b, int sg) {
+  return sg > 0 ? a + bf16x2{-b.y, b.x} : a + bf16x2{b.y, -b.x};
+}
+
+template <int MU, int SIG, class C>
+__device__ __forceinline__ void project(const C p[4][3], C h[2][3]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     if constexpr (MU == 0) {  // g_x psi = (i p3, i p2, -i p1, -i p0)
@@ -72,6 +94,31 @@ __device__ __forceinline__ void accumulate(Cplx<R> acc[4][3], const Cplx<R> w[2]
   }
 }
 
+// acc += sc * (spin reconstruction of w): the accumulate above with the
+// neighbour's per-site scale applied in the FP32 sum
+template <int MU, int SIG>
+__device__ __forceinline__ void accumulate_scaled(Cplx<float> acc[4][3], const Cplx<float> w[2][3], float sc) {
+  const float ps = SIG > 0 ? sc : -sc;  // +SIG*sc
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    acc[0][c] = {fmaf(sc, w[0][c].re, acc[0][c].re), fmaf(sc, w[0][c].im, acc[0][c].im)};
+    acc[1][c] = {fmaf(sc, w[1][c].re, acc[1][c].re), fmaf(sc, w[1][c].im, acc[1][c].im)};
+    if constexpr (MU == 0) {  // acc2 += -SIG i w1, acc3 += -SIG i w0
+      acc[2][c] = {fmaf(ps, w[1][c].im, acc[2][c].re), fmaf(-ps, w[1][c].re, acc[2][c].im)};
+      acc[3][c] = {fmaf(ps, w[0][c].im, acc[3][c].re), fmaf(-ps, w[0][c].re, acc[3][c].im)};
+    } else if constexpr (MU == 1) {  // acc2 += SIG w1, acc3 -= SIG w0
+      acc[2][c] = {fmaf(ps, w[1][c].re, acc[2][c].re), fmaf(ps, w[1][c].im, acc[2][c].im)};
+      acc[3][c] = {fmaf(-ps, w[0][c].re, acc[3][c].re), fmaf(-ps, w[0][c].im, acc[3][c].im)};
+    } else if constexpr (MU == 2) {  // acc2 += -SIG i w0, acc3 += SIG i w1
+      acc[2][c] = {fmaf(ps, w[0][c].im, acc[2][c].re), fmaf(-ps, w[0][c].re, acc[2][c].im)};
+      acc[3][c] = {fmaf(-ps, w[1][c].im, acc[3][c].re), fmaf(ps, w[1][c].re, acc[3][c].im)};
+    } else {  // acc2 += SIG w0, acc3 += SIG w1
+      acc[2][c] = {fmaf(ps, w[0][c].re, acc[2][c].re), fmaf(ps, w[0][c].im, acc[2][c].im)};
+      acc[3][c] = {fmaf(ps, w[1][c].re, acc[3][c].re), fmaf(ps, w[1][c].im, acc[3][c].im)};
+    }
+  }
+}
+
 // w = U h (fwd) or U^dag h (bwd), two colour vectors
 template <bool ADJ, class R>
 __device__ __forceinline__ void colour_mul(const Cplx<R> U[3][3], const Cplx<R> h[2][3], Cplx<R> w[2][3]) {
@@ -86,6 +133,58 @@ __device__ __forceinline__ void colour_mul(const Cplx<R> U[3][3], const Cplx<R> 
         s = add(s, t);
       }
       w[k][a] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Packed 16-bit hop (F16 and BF16 storage).  A neighbour's 12 complex numbers
+// stay in their stored (re, im) 16-bit pairs; the spin projection is formed on
+// the pairs (its sum rounded once to the storage format) and the colour
+// product uses dot2 instructions, whose 16 x 16-bit products are exact in FP32
+// and are summed in FP32.  The neighbour's per-site scale enters in the FP32
+// accumulation.  The staged link of a direction is V = U (forward) or U^dag
+// (backward), with the antiperiodic sign, as two pairs per entry:
+// (Re V, -Im V) and (Im V, Re V), so Re(V h) and Im(V h) are plain dot2 sums.
+// ---------------------------------------------------------------------------
+
+template <int P> struct Packed {
+  static constexpr bool enabled = false;
+};
+template <> struct Packed<F16> {
+  static constexpr bool enabled = true;
+  using T2 = f16x2;
+  static __device__ __forceinline__ float dot(T2 a, T2 b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
+  static __device__ __forceinline__ T2 make(float re, float im) { return T2{(_Float16)re, (_Float16)im}; }
+};
+template <> struct Packed<BF16> {
+  static constexpr bool enabled = true;
+  using T2 = bf16x2;
+  static __device__ __forceinline__ float dot(T2 a, T2 b, float c) {
+    return __builtin_amdgcn_fdot2_f32_bf16(a, b, c, false);
+  }
+  static __device__ __forceinline__ T2 make(float re, float im) { return T2{(__bf16)re, (__bf16)im}; }
+};
+
+// w = V h for the two projected colour vectors, V from the packed stage
+template <int P>
+__device__ __forceinline__ void colour_mul_packed(const uint32_t* lnk, int dir, int CB, int cbl,
+                                                  const typename Packed<P>::T2 h[2][3], Cplx<float> w[2][3]) {
+  using K = Packed<P>;
+  using T2 = typename K::T2;
+  const uint32_t* row = lnk + cbl * kStageLinkStride + dir * 18;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    T2 p1[3], p2[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      p1[b] = __builtin_bit_cast(T2, row[2 * (a * 3 + b)]);
+      p2[b] = __builtin_bit_cast(T2, row[2 * (a * 3 + b) + 1]);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      w[k][a].re = K::dot(p1[2], h[k][2], K::dot(p1[1], h[k][1], K::dot(p1[0], h[k][0], 0.f)));
+      w[k][a].im = K::dot(p2[2], h[k][2], K::dot(p2[1], h[k][1], K::dot(p2[0], h[k][0], 0.f)));
     }
   }
 }
@@ -130,12 +229,25 @@ __device__ __forceinline__ void pin_acc(Cplx<R> acc[4][3]) {
 
 // Per-workgroup staging of the stencil's geometry and links in LDS: for each
 // of the CB sites and 8 directions (mu forward 0..3, backward 4..7) the
-// neighbour's index (bit 31 = crosses the antiperiodic t boundary) and the
-// link's 12 reals, loaded once and shared by the site's L5 slice threads.
+// neighbour's index and the full 3x3 link (row 2 rebuilt once here instead of
+// once per slice thread), loaded once and shared by the site's L5 slice
+// threads.  A hop across the antiperiodic t boundary carries its -1 in the
+// staged link: U(-h) and (-U)h round identically.
 template <class R> struct Stage {
-  int* nbr;  // [8][CB]
-  R* lnk;    // [8*12][CB]
+  int* nbr;  // [CB][9]: dir
+  R* lnk;    // [CB][145]: dir * 18 + 2 * (3a + b) + (re | im)
 };
+
+template <class R>
+__device__ __forceinline__ void stage_link(const Stage<R>& st, int dir, int CB, int cbl, Cplx<R> U[3][3]) {
+  const R* row = st.lnk + cbl * kStageLinkStride + dir * 18;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) U[k / 3][k % 3] = {row[2 * k], row[2 * k + 1]};
+}
+__device__ __forceinline__ int stage_nbr(const int* nbr, int dir, int cbl) { return nbr[cbl * kStageNbrStride + dir]; }
+__host__ __device__ __forceinline__ size_t stage_nbr_bytes(int CB) {
+  return round_up((size_t)CB * kStageNbrStride * sizeof(int), 16);
+}
 
 template <int P>
 __device__ __forceinline__ void stage_fill(const DslashArgs& A, Stage<typename PrecTraits<P>::Real> st, int CB,
@@ -150,12 +262,12 @@ __device__ __forceinline__ void stage_fill(const DslashArgs& A, Stage<typename P
     R r[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) r[k] = 0;
+    bool flip = false;
     if (cb < g.Vh) {
       int X[4];
       site_coords(g, A.out_par, cb, X[0], X[1], X[2], X[3]);
       const int mu = dir & 3;
       const int Lmu = mu == 0 ? g.Lx : mu == 1 ? g.Ly : mu == 2 ? g.Lz : g.Lt;
-      bool flip;
       if (dir < 4) {
         flip = mu == 3 && g.tap && X[3] == g.Lt - 1;
         X[mu] = X[mu] + 1 == Lmu ? 0 : X[mu] + 1;
@@ -167,11 +279,102 @@ __device__ __forceinline__ void stage_fill(const DslashArgs& A, Stage<typename P
         nb = cb_index(g, X[0], X[1], X[2], X[3]);
         LinkIO<P>::load_raw(A.gauge, g.Vh, 1 - A.out_par, mu, nb, r);
       }
-      if (flip) nb |= (int)0x80000000u;
     }
-    st.nbr[dir * CB + cbl] = nb;
+    Cplx<R> U[3][3];
+    link_from_raw(r, U);
+    const R sg = flip ? R(-1) : R(1);
+    st.nbr[cbl * kStageNbrStride + dir] = nb;
+    R* row = st.lnk + cbl * kStageLinkStride + dir * 18;
+    if constexpr (Packed<P>::enabled) {
+      // V = U or U^dag as the pairs (Re V, -Im V), (Im V, Re V)
+      using K = Packed<P>;
+      uint32_t* pk = reinterpret_cast<uint32_t*>(row);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) st.lnk[(dir * 12 + k) * CB + cbl] = r[k];
+      for (int k = 0; k < 9; ++k) {
+        const int a = k / 3, b = k % 3;
+        const Cplx<R> u = dir < 4 ? U[a][b] : Cplx<R>{U[b][a].re, -U[b][a].im};
+        const R vr = sg * u.re, vi = sg * u.im;
+        pk[2 * k] = __builtin_bit_cast(uint32_t, K::make(vr, -vi));
+        pk[2 * k + 1] = __builtin_bit_cast(uint32_t, K::make(vi, vr));
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        row[2 * k] = sg * U[k / 3][k % 3].re;
+        row[2 * k + 1] = sg * U[k / 3][k % 3].im;
+      }
+    }
+  }
+}
+
+// load_bidiag (dag = 0) for 16-bit storage, with the three sites' scales
+// divided by their maximum m, which is returned: the combination stays O(1)
+// whatever the field's magnitude, so it can be rounded back to 16 bits.
+template <int P>
+__device__ __forceinline__ float load_bidiag_norm(const char* base, const FieldDesc& f, int cb, int s, int L5, float a,
+                                                  float b, float mq, float v[24]) {
+  int s_up = s - 1, s_dn = s + 1;
+  float b_up = b, b_dn = b;
+  if (s_up < 0) { s_up = L5 - 1; b_up = -b * mq; }
+  if (s_dn >= L5) { s_dn = 0; b_dn = -b * mq; }
+  using IO = SpinorIO<P>;
+  const float c0 = IO::scale(base, f, cb, s), cu = IO::scale(base, f, cb, s_up), cd = IO::scale(base, f, cb, s_dn);
+  const float m = fmaxf(c0, fmaxf(cu, cd));
+  const float im = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+  for (int g = 0; g < 3; ++g) IO::group(base, f, cb, s, g, a * c0 * im, v + 8 * g);
+  float t[16];
+  IO::group(base, f, cb, s_up, 0, b_up * cu * im, t);
+  IO::group(base, f, cb, s_up, 1, b_up * cu * im, t + 8);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) v[k] += t[k];
+  IO::group(base, f, cb, s_dn, 1, b_dn * cd * im, t);
+  IO::group(base, f, cb, s_dn, 2, b_dn * cd * im, t + 8);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) v[12 + k] += t[4 + k];
+  return m;
+}
+
+template <int P, bool DAG, bool PRO, int MU>
+__device__ __forceinline__ void hop_dir_packed(const DslashArgs& A, const FieldDesc& f, const char* in, int s,
+                                               const Coef5& c, Cplx<float> acc[4][3], Stage<float> st, int CB,
+                                               int cbl) {
+  using K = Packed<P>;
+  using T2 = typename K::T2;
+  constexpr int SF = DAG ? +1 : -1;
+  constexpr int SB = -SF;
+  const uint32_t* lnk = reinterpret_cast<const uint32_t*>(st.lnk);
+#pragma unroll
+  for (int fb = 0; fb < 2; ++fb) {
+    const int nb = stage_nbr(st.nbr, MU + 4 * fb, cbl);
+    T2 h[2][3];
+    float sc;
+    if constexpr (PRO) {
+      float v[24];
+      sc = load_bidiag_norm<P>(in, f, nb, s, A.g.L5, (float)c.b5, (float)c.c5, (float)c.mq, v);
+      Cplx<float> pf[4][3], hf[2][3];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) pf[k / 3][k % 3] = {v[2 * k], v[2 * k + 1]};
+      if (fb == 0) project<MU, SF>(pf, hf);
+      else project<MU, SB>(pf, hf);
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) h[k][a] = K::make(hf[k][a].re, hf[k][a].im);
+    } else {
+      uint32_t q[12];
+      SpinorIO<P>::load_packed(in, f, nb, s, q, sc);
+      T2 psi[4][3];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = __builtin_bit_cast(T2, q[k]);
+      if (fb == 0) project<MU, SF>(psi, h);
+      else project<MU, SB>(psi, h);
+    }
+    Cplx<float> w[2][3];
+    colour_mul_packed<P>(lnk, MU + 4 * fb, CB, cbl, h, w);
+    if (fb == 0) accumulate_scaled<MU, SF>(acc, w, sc);
+    else accumulate_scaled<MU, SB>(acc, w, sc);
+    pin_acc(acc);
   }
 }
 
@@ -192,13 +395,9 @@ __device__ __forceinline__ void hop_dir_single(const DslashArgs& A, const FieldD
     int nb;
     bool flip;
     if constexpr (STAGE) {
-      const int e = st.nbr[(MU + 4 * fb) * CB + cbl];
-      nb = e & 0x7fffffff;
-      flip = e < 0;
-      R r[12];
-#pragma unroll
-      for (int k = 0; k < 12; ++k) r[k] = st.lnk[((MU + 4 * fb) * 12 + k) * CB + cbl];
-      link_from_raw(r, U);
+      nb = stage_nbr(st.nbr, MU + 4 * fb, cbl);
+      flip = false;  // carried by the staged link
+      stage_link(st, MU + 4 * fb, CB, cbl, U);
     } else {
       int Y[4] = {X[0], X[1], X[2], X[3]};
       if (fb == 0) {
@@ -248,33 +447,24 @@ __device__ __forceinline__ void hop_dir_pair(const DslashArgs& A, const FieldDes
   constexpr int SF = DAG ? +1 : -1;
   constexpr int SB = -SF;
   R v0[24], v1[24];
-  const int e0 = st.nbr[MU * CB + cbl];
-  const int e1 = st.nbr[(MU + 4) * CB + cbl];
+  const int e0 = stage_nbr(st.nbr, MU, cbl);
+  const int e1 = stage_nbr(st.nbr, MU + 4, cbl);
   if constexpr (PRO) {
-    load_bidiag<P>(in, f, e0 & 0x7fffffff, s, g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v0);
-    load_bidiag<P>(in, f, e1 & 0x7fffffff, s, g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v1);
+    load_bidiag<P>(in, f, e0, s, g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v0);
+    load_bidiag<P>(in, f, e1, s, g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v1);
   } else {
-    SpinorIO<P>::load(in, f, e0 & 0x7fffffff, s, v0);
-    SpinorIO<P>::load(in, f, e1 & 0x7fffffff, s, v1);
+    SpinorIO<P>::load(in, f, e0, s, v0);
+    SpinorIO<P>::load(in, f, e1, s, v1);
   }
   Cplx<R> U[3][3], psi[4][3], h[2][3], w[2][3];
 #pragma unroll
   for (int fb = 0; fb < 2; ++fb) {
     const R* v = fb == 0 ? v0 : v1;
-    R r[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) r[k] = st.lnk[((MU + 4 * fb) * 12 + k) * CB + cbl];
-    link_from_raw(r, U);
+    stage_link(st, MU + 4 * fb, CB, cbl, U);
 #pragma unroll
     for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = {v[2 * k], v[2 * k + 1]};
     if (fb == 0) project<MU, SF>(psi, h);
     else project<MU, SB>(psi, h);
-    if ((fb == 0 ? e0 : e1) < 0) {
-#pragma unroll
-      for (int k = 0; k < 2; ++k)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) h[k][a] = {-h[k][a].re, -h[k][a].im};
-    }
     if (fb == 0) {
       colour_mul<false>(U, h, w);
       accumulate<MU, SF>(acc, w);
@@ -294,12 +484,12 @@ template <int P, bool PRO>
 __device__ __forceinline__ void pipe_load(const DslashArgs& A, const FieldDesc& f, const char* in, int s,
                                           const Coef5& c, int e, typename PrecTraits<P>::Real v[24]) {
   using R = typename PrecTraits<P>::Real;
-  if constexpr (PRO) load_bidiag<P>(in, f, e & 0x7fffffff, s, A.g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v);
-  else SpinorIO<P>::load(in, f, e & 0x7fffffff, s, v);
+  if constexpr (PRO) load_bidiag<P>(in, f, e, s, A.g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v);
+  else SpinorIO<P>::load(in, f, e, s, v);
 }
 
 template <int P, bool DAG, int K>
-__device__ __forceinline__ void pipe_compute(const typename PrecTraits<P>::Real v[24], int e,
+__device__ __forceinline__ void pipe_compute(const typename PrecTraits<P>::Real v[24],
                                              Cplx<typename PrecTraits<P>::Real> acc[4][3],
                                              Stage<typename PrecTraits<P>::Real> st, int CB, int cbl) {
   using R = typename PrecTraits<P>::Real;
@@ -308,19 +498,10 @@ __device__ __forceinline__ void pipe_compute(const typename PrecTraits<P>::Real 
   constexpr int SF = DAG ? +1 : -1;
   constexpr int SIG = FB == 0 ? SF : -SF;
   Cplx<R> U[3][3], psi[4][3], h[2][3], w[2][3];
-  R r[12];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) r[k] = st.lnk[((MU + 4 * FB) * 12 + k) * CB + cbl];
-  link_from_raw(r, U);
+  stage_link(st, MU + 4 * FB, CB, cbl, U);
 #pragma unroll
   for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = {v[2 * k], v[2 * k + 1]};
   project<MU, SIG>(psi, h);
-  if (e < 0) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) h[k][a] = {-h[k][a].re, -h[k][a].im};
-  }
   colour_mul<FB == 1>(U, h, w);
   accumulate<MU, SIG>(acc, w);
 }
@@ -331,13 +512,12 @@ __device__ __forceinline__ void pipe_step(const DslashArgs& A, const FieldDesc& 
                                           Stage<typename PrecTraits<P>::Real> st, int CB, int cbl,
                                           typename PrecTraits<P>::Real cur[24], typename PrecTraits<P>::Real nxt[24]) {
   // neighbour order K = 2*mu + fb; stage index = mu + 4*fb
-  const int e = st.nbr[((K >> 1) + 4 * (K & 1)) * CB + cbl];
   if constexpr (K < 7) {
     constexpr int K1 = K + 1;
-    const int e1 = st.nbr[((K1 >> 1) + 4 * (K1 & 1)) * CB + cbl];
+    const int e1 = stage_nbr(st.nbr, (K1 >> 1) + 4 * (K1 & 1), cbl);
     pipe_load<P, PRO>(A, f, in, s, c, e1, nxt);
   }
-  pipe_compute<P, DAG, K>(cur, e, acc, st, CB, cbl);
+  pipe_compute<P, DAG, K>(cur, acc, st, CB, cbl);
   pin_acc(acc);
 }
 
@@ -347,7 +527,7 @@ __device__ __forceinline__ void hop_pipelined(const DslashArgs& A, const FieldDe
                                               Stage<typename PrecTraits<P>::Real> st, int CB, int cbl) {
   using R = typename PrecTraits<P>::Real;
   R a[24], b[24];
-  pipe_load<P, PRO>(A, f, in, s, c, st.nbr[0 * CB + cbl], a);
+  pipe_load<P, PRO>(A, f, in, s, c, stage_nbr(st.nbr, 0, cbl), a);
   pipe_step<P, DAG, PRO, 0>(A, f, in, s, c, acc, st, CB, cbl, a, b);
   pipe_step<P, DAG, PRO, 1>(A, f, in, s, c, acc, st, CB, cbl, b, a);
   pipe_step<P, DAG, PRO, 2>(A, f, in, s, c, acc, st, CB, cbl, a, b);
@@ -370,57 +550,70 @@ template <int P, bool DAG, bool PRO, bool STAGE, int MU>
 __device__ __forceinline__ void hop_dir(const DslashArgs& A, const FieldDesc& f, const char* in, int cb, int s,
                                         const int X[4], const Coef5& c, Cplx<typename PrecTraits<P>::Real> acc[4][3],
                                         Stage<typename PrecTraits<P>::Real> st, int CB, int cbl) {
-  if constexpr (STAGE && MDWF_HOP_PAIR) hop_dir_pair<P, DAG, PRO, MU>(A, f, in, s, c, acc, st, CB, cbl);
+  if constexpr (STAGE && Packed<P>::enabled) hop_dir_packed<P, DAG, PRO, MU>(A, f, in, s, c, acc, st, CB, cbl);
+  else if constexpr (STAGE && MDWF_HOP_PAIR) hop_dir_pair<P, DAG, PRO, MU>(A, f, in, s, c, acc, st, CB, cbl);
   else hop_dir_single<P, DAG, PRO, STAGE, MU>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
 }
 
 // ---------------------------------------------------------------------------
 // fifth-dimension chains on one complex component column held in LDS.
-// lds layout: [(s*24 + 2*comp + reim) * CB + cbl].
+// lds layout: [(s*CB + cbl) * 25 + 2*comp + reim] (one padded row per
+// 5D site: immediate offsets, conflict-free rows).
 // "lower" orientation: the operator couples s to s-1 (P+ of P5, or P- of
 // P5^T); otherwise the column is walked from the top with i = L5-1-s.
 // ---------------------------------------------------------------------------
+constexpr int kChainStride = 25;
+// A column walked from i = 0 (s = 0 when "lower", s = L5 - 1 otherwise).
 template <class R> struct Column {
-  R* lds;
-  int base;  // offset of (s = 0, comp) for this cbl
-  int CB;
+  R* p0;
+  int step;  // signed distance between consecutive i, in elements
   int L5;
-  bool lower;
-  __device__ __forceinline__ int off(int i) const { return base + (lower ? i : (L5 - 1 - i)) * 24 * CB; }
-  __device__ __forceinline__ Cplx<R> get(int i) const { const int o = off(i); return {lds[o], lds[o + CB]}; }
-  __device__ __forceinline__ void set(int i, Cplx<R> v) const { const int o = off(i); lds[o] = v.re; lds[o + CB] = v.im; }
+  __device__ __forceinline__ Cplx<R> get(int i) const { const R* q = p0 + i * step; return {q[0], q[1]}; }
+  __device__ __forceinline__ void set(int i, Cplx<R> v) const { R* q = p0 + i * step; q[0] = v.re; q[1] = v.im; }
 };
 
-// y = M5^-1 x on a column, in place
-template <class R> __device__ __forceinline__ void col_m5inv(const Column<R>& col, const Coef5& c) {
+// y = M5^-1 x on a column, in place; with BIDIAG the column is then replaced
+// by z = a*y + b*(shift y) (the lower bidiagonal with the -mq wall), fused
+// into the same sweep: z_i needs y_i and y_{i-1}, z_0 needs y_{L5-1}.
+template <class R, bool BIDIAG>
+__device__ __forceinline__ void col_m5inv(const Column<R>& col, const Coef5& c, R a, R b) {
   const R kappa = (R)c.kappa, mq = (R)c.mq;
+  const int L5 = col.L5;
   R pw = 1, wr = 0, wi = 0;
-  for (int k = 1; k < col.L5; ++k) {
+  for (int k = 1; k < L5; ++k) {
     pw *= -kappa;
-    const Cplx<R> x = col.get(col.L5 - k);
+    const Cplx<R> x = col.get(L5 - k);
     wr += pw * x.re;
     wi += pw * x.im;
   }
   const Cplx<R> x0 = col.get(0);
   const R ic = (R)c.inv_c, ia = (R)c.inv_alpha;
   Cplx<R> prev = {(x0.re - mq * wr) * ic, (x0.im - mq * wi) * ic};
-  col.set(0, {prev.re * ia, prev.im * ia});
-  for (int i = 1; i < col.L5; ++i) {
+  const Cplx<R> y0 = {prev.re * ia, prev.im * ia};
+  Cplx<R> ym = y0;
+  if constexpr (!BIDIAG) col.set(0, y0);
+  for (int i = 1; i < L5; ++i) {
     const Cplx<R> x = col.get(i);
     prev = {x.re - kappa * prev.re, x.im - kappa * prev.im};
-    col.set(i, {prev.re * ia, prev.im * ia});
+    const Cplx<R> y = {prev.re * ia, prev.im * ia};
+    if constexpr (BIDIAG) col.set(i, {a * y.re + b * ym.re, a * y.im + b * ym.im});
+    else col.set(i, y);
+    ym = y;
   }
+  if constexpr (BIDIAG) col.set(0, {a * y0.re - b * mq * ym.re, a * y0.im - b * mq * ym.im});
 }
 
 // z = a*y + b*(shift y), shift the lower bidiagonal with the -mq wall, in place
 template <class R> __device__ __forceinline__ void col_bidiag(const Column<R>& col, R a, R b, R mq) {
-  const Cplx<R> last = col.get(col.L5 - 1);
-  for (int i = col.L5 - 1; i >= 1; --i) {
-    const Cplx<R> y = col.get(i), ym = col.get(i - 1);
+  const int L5 = col.L5;
+  const Cplx<R> last = col.get(L5 - 1);
+  Cplx<R> y = last;
+  for (int i = L5 - 1; i >= 1; --i) {
+    const Cplx<R> ym = col.get(i - 1);
     col.set(i, {a * y.re + b * ym.re, a * y.im + b * ym.im});
+    y = ym;
   }
-  const Cplx<R> y0 = col.get(0);
-  col.set(0, {a * y0.re - b * mq * last.re, a * y0.im - b * mq * last.im});
+  col.set(0, {a * y.re - b * mq * last.re, a * y.im - b * mq * last.im});
 }
 
 template <class R>
@@ -430,11 +623,13 @@ __device__ __forceinline__ void run_chain(R* lds, int op, int CB, int cb_log2, i
     const int cbl = task & (CB - 1);
     const int j = task >> cb_log2;
     const bool plus = j < 6;
-    Column<R> col{lds, 2 * j * CB + cbl, CB, L5, plus != dag};
+    const int stride = kChainStride * CB;
+    R* base = lds + cbl * kChainStride + 2 * j;
+    const Column<R> col = (plus != dag) ? Column<R>{base, stride, L5} : Column<R>{base + (L5 - 1) * stride, -stride, L5};
     switch (op) {
       case CH_M5INV:
       case CH_M5INV_DAG:
-        col_m5inv(col, c);
+        col_m5inv<R, false>(col, c, R(0), R(0));
         break;
       case CH_MPHI:
       case CH_MPHI_DAG:
@@ -446,8 +641,7 @@ __device__ __forceinline__ void run_chain(R* lds, int op, int CB, int cb_log2, i
         break;
       case CH_MPHI_M5INV:
       case CH_MPHIDAG_M5INVDAG:
-        col_m5inv(col, c);
-        col_bidiag(col, (R)c.b5, (R)c.c5, (R)c.mq);
+        col_m5inv<R, true>(col, c, (R)c.b5, (R)c.c5);
         break;
       default:
         break;
@@ -456,12 +650,14 @@ __device__ __forceinline__ void run_chain(R* lds, int op, int CB, int cb_log2, i
 }
 
 template <class R> __device__ __forceinline__ void lds_put(R* lds, int CB, int cbl, int s, const R v[24]) {
+  R* row = lds + (s * CB + cbl) * kChainStride;
 #pragma unroll
-  for (int k = 0; k < 24; ++k) lds[(s * 24 + k) * CB + cbl] = v[k];
+  for (int k = 0; k < 24; ++k) row[k] = v[k];
 }
 template <class R> __device__ __forceinline__ void lds_get(const R* lds, int CB, int cbl, int s, R v[24]) {
+  const R* row = lds + (s * CB + cbl) * kChainStride;
 #pragma unroll
-  for (int k = 0; k < 24; ++k) v[k] = lds[(s * 24 + k) * CB + cbl];
+  for (int k = 0; k < 24; ++k) v[k] = row[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -515,7 +711,7 @@ __global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
   const int L5 = A.g.L5;
 
   Stage<R> st{reinterpret_cast<int*>(smem + A.lds_stage_off),
-              reinterpret_cast<R*>(smem + A.lds_stage_off + (size_t)8 * CB * sizeof(int))};
+              reinterpret_cast<R*>(smem + A.lds_stage_off + stage_nbr_bytes(CB))};
   if constexpr (HOP && STAGE) {
     stage_fill<P>(A, st, CB, A.cb_log2, cb0, tid, nthr);
     __syncthreads();
@@ -534,7 +730,7 @@ __global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
 #pragma unroll
         for (int b = 0; b < 3; ++b) acc[a][b] = {0, 0};
       const char* in = A.in[slot];
-      if constexpr (STAGE && MDWF_HOP_PIPE) {
+      if constexpr (STAGE && MDWF_HOP_PIPE && !Packed<P>::enabled) {
         hop_pipelined<P, DAG, PRO>(A, f, in, s, c, acc, st, CB, cbl);
       } else {
         hop_dir<P, DAG, PRO, STAGE, 0>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
@@ -554,6 +750,7 @@ __global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
 
   R* lds = reinterpret_cast<R*>(smem);
   if (A.c1 != CH_NONE) {
+    if constexpr (HOP && STAGE) __syncthreads();  // the chain columns overlay the stage
     lds_put(lds, CB, cbl, s, v);
     __syncthreads();
     run_chain(lds, A.c1, CB, A.cb_log2, L5, c, tid, nthr);
@@ -662,20 +859,21 @@ static hipError_t launch_p(const DslashArgs& A, bool hop, bool dag, bool pro, in
 
 int dslash_max_threads(int prec) { return prec == F64 ? kMaxThreads<F64> : kMaxThreads<F32>; }
 
-// LDS: [fifth-dimension chain columns][reduction][stage: neighbours + links]
+// LDS: [stage (neighbours + links) | fifth-dimension chain columns][reduction].
+// The stage is dead once the hop is done, so the chain columns overlay it.
 static void lds_layout(const DslashArgs& A, int prec, int cb_log2, bool hop, size_t& chain, size_t& red,
                        size_t& stage) {
   const size_t CB = (size_t)1 << cb_log2;
   const size_t rb = prec == F64 ? 8 : 4;
-  chain = (A.c1 != CH_NONE || A.c2 != CH_NONE) ? round_up(CB * A.g.L5 * 24 * rb, 16) : 0;
+  chain = (A.c1 != CH_NONE || A.c2 != CH_NONE) ? round_up(CB * A.g.L5 * kChainStride * rb, 16) : 0;
   red = A.reduce ? round_up(CB * A.g.L5 * 8, 16) : 0;
-  stage = (hop && A.stage) ? round_up(CB * 8 * 4, 16) + CB * 8 * 12 * rb : 0;
+  stage = (hop && A.stage) ? round_up(stage_nbr_bytes((int)CB) + CB * kStageLinkStride * rb, 16) : 0;
 }
 
 size_t dslash_lds_bytes(const DslashArgs& A, int prec, int cb_log2, bool hop) {
   size_t chain, red, stage;
   lds_layout(A, prec, cb_log2, hop, chain, red, stage);
-  return chain + red + stage;
+  return std::max(chain, stage) + red;
 }
 
 hipError_t dslash_launch(DslashArgs A, int prec, bool hop, bool dag, bool pro, int cb_log2, hipStream_t st) {
@@ -686,9 +884,9 @@ hipError_t dslash_launch(DslashArgs A, int prec, bool hop, bool dag, bool pro, i
   if (A.order_bt > 0 && (plane % CB != 0 || A.g.Lt % A.order_bt != 0)) A.order_bt = 0;
   size_t chain, red, stage;
   lds_layout(A, prec, cb_log2, hop, chain, red, stage);
-  A.lds_chain_bytes = (int)chain;
-  A.lds_stage_off = (int)(chain + red);
-  const size_t smem = chain + red + stage;
+  A.lds_chain_bytes = (int)std::max(chain, stage);  // offset of the reduction area
+  A.lds_stage_off = 0;
+  const size_t smem = std::max(chain, stage) + red;
   const int threads = CB * A.g.L5;
   const long long blocks = (long long)A.nblk * A.nslots;
   const int grid = (int)round_up((size_t)blocks, 8);

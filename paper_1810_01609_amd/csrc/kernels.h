@@ -47,7 +47,7 @@ struct DslashArgs {
   int nslots;
   int nblk;                // filled by the launcher
   int cb_log2;             // filled by the launcher
-  int lds_chain_bytes;     // filled by the launcher
+  int lds_chain_bytes;     // filled by the launcher: offset of the reduction area
   int lds_stage_off;       // filled by the launcher
   int stage;               // 1: stage neighbour indices and links in LDS once per workgroup
   int order_bt;            // > 0: blocked (z, t) plane traversal with Bt time slices per block
