@@ -69,6 +69,11 @@ __global__ __launch_bounds__(kBlasThreads) void k_cg_xr(BlasArgs A) {
   if (threadIdx.x == 0) A.partials[(size_t)slot * A.nblk + blockIdx.x] = t;
 }
 
+// p = r + beta p on every slice of a 4D site, and pt = M_phi p from the
+// new p: (M_phi p)_s = b5 p_s + c5 (P5 p)_s, P5 taking spins 0,1 from slice
+// s - 1 and spins 2,3 from slice s + 1, the wall hop carrying -mq.  pt is the
+// input of the first stencil launch of the next iteration, which then needs
+// no fifth-dimension prologue on its eight neighbours.
 template <int PS>
 __global__ __launch_bounds__(kBlasThreads) void k_cg_p(BlasArgs A) {
   using RS = typename PrecTraits<PS>::Real;
@@ -78,17 +83,46 @@ __global__ __launch_bounds__(kBlasThreads) void k_cg_p(BlasArgs A) {
   const int cb = blockIdx.x * kBlasThreads + threadIdx.x;
   if (cb >= A.g.Vh) return;
   const FieldDesc f{A.g.Vh, A.g.L5};
+  const int L5 = A.g.L5;
   const RS beta = (RS)S.beta;
+  const Coef5 c = A.coef[slot];
+  const RS b5 = (RS)c.b5, c5 = (RS)c.c5, wall = (RS)(-c.c5 * c.mq);
   char* p = A.a[slot];
   const char* r = A.b[slot];
-  for (int s = 0; s < A.g.L5; ++s) {
-    RS pv[24], rv[24];
-    SpinorIO<PS>::load(p, f, cb, s, pv);
+  char* pt = A.c[slot];
+  RS cur[24], rv[24];
+  // spins 0,1 of the new p on slice L5 - 1 feed slice 0 across the wall
+  SpinorIO<PS>::load(p, f, cb, L5 - 1, cur);
+  SpinorIO<PS>::load(r, f, cb, L5 - 1, rv);
+  RS up[12];  // c5 (P5 p)_s, spins 0,1
+#pragma unroll
+  for (int k = 0; k < 12; ++k) up[k] = wall * (rv[k] + beta * cur[k]);
+  RS first_dn[12], pend[24];
+  for (int s = 0; s < L5; ++s) {
+    SpinorIO<PS>::load(p, f, cb, s, cur);
     SpinorIO<PS>::load(r, f, cb, s, rv);
 #pragma unroll
-    for (int k = 0; k < 24; ++k) pv[k] = rv[k] + beta * pv[k];
-    SpinorIO<PS>::store(p, f, cb, s, pv);
+    for (int k = 0; k < 24; ++k) cur[k] = rv[k] + beta * cur[k];
+    SpinorIO<PS>::store(p, f, cb, s, cur);
+    if (s == 0) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) first_dn[k] = cur[12 + k];
+    } else {
+      // finish pt_{s-1}: spins 2,3 take c5 p_s
+#pragma unroll
+      for (int k = 0; k < 12; ++k) pend[12 + k] += c5 * cur[12 + k];
+      SpinorIO<PS>::store(pt, f, cb, s - 1, pend);
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      pend[k] = b5 * cur[k] + up[k];
+      pend[12 + k] = b5 * cur[12 + k];
+      up[k] = c5 * cur[k];
+    }
   }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) pend[12 + k] += wall * first_dn[k];
+  SpinorIO<PS>::store(pt, f, cb, L5 - 1, pend);
 }
 
 template <int PI, int PO>

@@ -265,9 +265,11 @@ static void candidates(const Geom& g, int prec, DslashArgs A, bool hop, std::vec
     const size_t lds = dslash_lds_bytes(A, prec, lg, hop);
     if (lds > 160 * 1024) break;
     out.push_back(lg | (stage << 8));
-    if (lds <= 64 * 1024 && CB <= 64) dflt = lg | (stage << 8);
   }
-  if (dflt < 0 && !out.empty()) dflt = out.front();
+  // untuned default: the smallest workgroup (16 sites x L5 slices) — it packs
+  // the most resident waves per CU under the LDS and register limits, and the
+  // tuner picks it for nearly every kernel and lattice measured
+  if (!out.empty()) dflt = out.front();
 }
 
 static double prog_bytes(const Geom& g, int prec, const Prog& p, int nslots, bool cg) {

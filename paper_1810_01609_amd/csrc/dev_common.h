@@ -157,8 +157,18 @@ template <int P> __device__ __forceinline__ void unpack2(uint32_t w, float& a, f
   a = h_to_f<P>(w & 0xffffu);
   b = h_to_f<P>(w >> 16);
 }
+// two values rounded to nearest-even into one 32-bit word (first value in the
+// low half); F16 and BF16 use the packed conversion instructions
 template <int P> __device__ __forceinline__ uint32_t pack2(float a, float b) {
-  return f_to_h<P>(a) | (f_to_h<P>(b) << 16);
+  if constexpr (P == F16) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, h2{(_Float16)a, (_Float16)b});
+  } else if constexpr (P == BF16) {
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, b2{(__bf16)a, (__bf16)b});
+  } else {
+    return f_to_h<P>(a) | (f_to_h<P>(b) << 16);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -236,12 +246,21 @@ template <int P> struct SpinorIO16 {
   }
   static __device__ __forceinline__ void group(const char* base, const FieldDesc& f, int cb, int s, int g, float sc, R* v) {
     const v4u q = ldg<v4u>(reinterpret_cast<const uint4*>(base) + ((size_t)s * 3 + g) * f.Vh + cb);
-    unpack2<P>(q.x, v[0], v[1]);
-    unpack2<P>(q.y, v[2], v[3]);
-    unpack2<P>(q.z, v[4], v[5]);
-    unpack2<P>(q.w, v[6], v[7]);
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+    if constexpr (P == I16) {
+      // q/32767 * sc as q * (sc/32767): one multiply per value
+      const float scq = sc * (1.0f / 32767.0f);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] *= sc;
+      for (int k = 0; k < 4; ++k) {
+        v[2 * k] = (float)(int16_t)(uint16_t)(w[k] & 0xffffu) * scq;
+        v[2 * k + 1] = (float)(int16_t)(uint16_t)(w[k] >> 16) * scq;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) unpack2<P>(w[k], v[2 * k], v[2 * k + 1]);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] *= sc;
+    }
   }
   static __device__ __forceinline__ void load(const char* base, const FieldDesc& f, int cb, int s, R v[24]) {
     const float sc = scale(base, f, cb, s);

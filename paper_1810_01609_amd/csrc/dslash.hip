@@ -155,6 +155,13 @@ template <> struct Packed<F16> {
   static constexpr bool enabled = true;
   using T2 = f16x2;
   static __device__ __forceinline__ float dot(T2 a, T2 b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
+  // the first product of a chain: the three-operand form with a zero addend
+  // (the builtin becomes a register clear plus the accumulating form)
+  static __device__ __forceinline__ float dot0(T2 a, T2 b) {
+    float r;
+    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+  }
   static __device__ __forceinline__ T2 make(float re, float im) { return T2{(_Float16)re, (_Float16)im}; }
 };
 template <> struct Packed<BF16> {
@@ -162,6 +169,11 @@ template <> struct Packed<BF16> {
   using T2 = bf16x2;
   static __device__ __forceinline__ float dot(T2 a, T2 b, float c) {
     return __builtin_amdgcn_fdot2_f32_bf16(a, b, c, false);
+  }
+  static __device__ __forceinline__ float dot0(T2 a, T2 b) {
+    float r;
+    asm("v_dot2_f32_bf16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+    return r;
   }
   static __device__ __forceinline__ T2 make(float re, float im) { return T2{(__bf16)re, (__bf16)im}; }
 };
@@ -183,8 +195,8 @@ __device__ __forceinline__ void colour_mul_packed(const uint32_t* lnk, int dir, 
     }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      w[k][a].re = K::dot(p1[2], h[k][2], K::dot(p1[1], h[k][1], K::dot(p1[0], h[k][0], 0.f)));
-      w[k][a].im = K::dot(p2[2], h[k][2], K::dot(p2[1], h[k][1], K::dot(p2[0], h[k][0], 0.f)));
+      w[k][a].re = K::dot(p1[2], h[k][2], K::dot(p1[1], h[k][1], K::dot0(p1[0], h[k][0])));
+      w[k][a].im = K::dot(p2[2], h[k][2], K::dot(p2[1], h[k][1], K::dot0(p2[0], h[k][0])));
     }
   }
 }
@@ -575,6 +587,9 @@ template <class R> struct Column {
 // y = M5^-1 x on a column, in place; with BIDIAG the column is then replaced
 // by z = a*y + b*(shift y) (the lower bidiagonal with the -mq wall), fused
 // into the same sweep: z_i needs y_i and y_{i-1}, z_0 needs y_{L5-1}.
+// The sweeps read four column entries before writing any, so the LDS reads
+// of a batch are in flight together (the in-place writes would otherwise
+// order every read behind the previous write).
 template <class R, bool BIDIAG>
 __device__ __forceinline__ void col_m5inv(const Column<R>& col, const Coef5& c, R a, R b) {
   const R kappa = (R)c.kappa, mq = (R)c.mq;
@@ -592,14 +607,22 @@ __device__ __forceinline__ void col_m5inv(const Column<R>& col, const Coef5& c, 
   const Cplx<R> y0 = {prev.re * ia, prev.im * ia};
   Cplx<R> ym = y0;
   if constexpr (!BIDIAG) col.set(0, y0);
-  for (int i = 1; i < L5; ++i) {
-    const Cplx<R> x = col.get(i);
+  auto step = [&](int i, Cplx<R> x) {
     prev = {x.re - kappa * prev.re, x.im - kappa * prev.im};
     const Cplx<R> y = {prev.re * ia, prev.im * ia};
     if constexpr (BIDIAG) col.set(i, {a * y.re + b * ym.re, a * y.im + b * ym.im});
     else col.set(i, y);
     ym = y;
+  };
+  int i = 1;
+  for (; i + 3 < L5; i += 4) {
+    const Cplx<R> x1 = col.get(i), x2 = col.get(i + 1), x3 = col.get(i + 2), x4 = col.get(i + 3);
+    step(i, x1);
+    step(i + 1, x2);
+    step(i + 2, x3);
+    step(i + 3, x4);
   }
+  for (; i < L5; ++i) step(i, col.get(i));
   if constexpr (BIDIAG) col.set(0, {a * y0.re - b * mq * ym.re, a * y0.im - b * mq * ym.im});
 }
 
@@ -608,11 +631,19 @@ template <class R> __device__ __forceinline__ void col_bidiag(const Column<R>& c
   const int L5 = col.L5;
   const Cplx<R> last = col.get(L5 - 1);
   Cplx<R> y = last;
-  for (int i = L5 - 1; i >= 1; --i) {
-    const Cplx<R> ym = col.get(i - 1);
+  auto step = [&](int i, Cplx<R> ym) {
     col.set(i, {a * y.re + b * ym.re, a * y.im + b * ym.im});
     y = ym;
+  };
+  int i = L5 - 1;
+  for (; i - 3 >= 1; i -= 4) {
+    const Cplx<R> y1 = col.get(i - 1), y2 = col.get(i - 2), y3 = col.get(i - 3), y4 = col.get(i - 4);
+    step(i, y1);
+    step(i - 1, y2);
+    step(i - 2, y3);
+    step(i - 3, y4);
   }
+  for (; i >= 1; --i) step(i, col.get(i - 1));
   col.set(0, {a * y.re - b * mq * last.re, a * y.im - b * mq * last.im});
 }
 

@@ -91,7 +91,7 @@ struct mdwf_job {
   mdwf::Coef5 coef{};
   void* block = nullptr;
   size_t block_bytes = 0;
-  std::vector<char*> fx, fr, fp, ft, fv, fxh, feh;
+  std::vector<char*> fx, fr, fp, fpt, ft, fv, fxh, feh;  // fpt = M_phi p
   std::vector<mdwf::CGState> st;
   std::vector<mdwf_cg_stats> stats;
   std::vector<int> finished;

@@ -20,6 +20,8 @@ namespace mdwf {
 Prog prog_D(int par) { return Prog{true, false, true, CH_NONE, CH_NONE, AUX_M5, 0, -0.5, par}; }
 Prog prog_Ddag(int par) { return Prog{true, true, false, CH_MPHI_DAG, CH_NONE, AUX_M5DAG, 0, -0.5, par}; }
 Prog prog_A1() { return Prog{true, false, true, CH_MPHI_M5INV, CH_NONE, AUX_NONE, 0, 1.0, 1}; }
+// A1 on an input that already holds M_phi p (the CG loop's p-update writes it)
+Prog prog_A1_pt() { return Prog{true, false, false, CH_MPHI_M5INV, CH_NONE, AUX_NONE, 0, 1.0, 1}; }
 Prog prog_A2(bool with_c2, bool reduce) {
   return Prog{true, false, false, CH_M5INV, with_c2 ? CH_M5INV_DAG : CH_NONE, AUX_PLAIN, reduce ? 1 : 0, -0.25, 0};
 }

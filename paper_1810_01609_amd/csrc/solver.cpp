@@ -30,6 +30,7 @@ using namespace mdwf;
 namespace mdwf {
 Prog prog_D(int par);
 Prog prog_A1();
+Prog prog_A1_pt();
 Prog prog_A2(bool with_c2, bool reduce);
 Prog prog_B1();
 Prog prog_B2();
@@ -55,7 +56,7 @@ SlotLayout slot_layout(const Geom& g, int ps) {
   L.fx = round_up(spinor_field_bytes(inner_x_prec(ps), g.L5, g.Vh), 256);
   L.fxh = ps == F64 ? 0 : round_up(spinor_field_bytes(F64, g.L5, g.Vh), 256);
   L.feh = round_up(spinor_field_bytes(F64, g.L5, g.Vh), 256);  // eta^_e, kept for reliable updates
-  L.total = 4 * L.fs + L.fx + L.fxh + L.feh;
+  L.total = 5 * L.fs + L.fx + L.fxh + L.feh;  // r, p, M_phi p, t, v
   return L;
 }
 
@@ -65,8 +66,8 @@ void iter_model(const Geom& g, int ps, double& bytes, double& flops) {
   const double sb = spinor_site_bytes(ps), sx = spinor_site_bytes(inner_x_prec(ps));
   const double links = 8.0 * g.Vh * 12.0 * link_real_bytes(ps);
   // A1 2, A2 3, B1 2, B2 with the fused update 5 spinor transfers + x read/write,
-  // 4 link sweeps; p = r + beta p 3 transfers
-  bytes = ne * sb * 12 + 2 * ne * sx + 4 * links + ne * 3 * sb;
+  // 4 link sweeps; p = r + beta p with M_phi p 4 transfers
+  bytes = ne * sb * 12 + 2 * ne * sx + 4 * links + ne * 4 * sb;
   // hop 1320/site x4, M_phi 72 x3, M5^-1 96 x4, M5 72, xpay 48 x2, CG BLAS 192
   flops = ne * (4 * 1320.0 + 3 * 72 + 4 * 96 + 72 + 2 * 48 + 192);
 }
@@ -132,27 +133,47 @@ struct One {
   Geom geom;
   const Coef5* coef_d;
   hipError_t e = hipSuccess;
-  char* const* tab(const void* p) { return upload_table(c, std::vector<const void*>{p}); }
+  // a one-entry device pointer table; a failed upload turns into an error
+  // here instead of a null table reaching a kernel
+  char* const* tab(const void* p) {
+    char* const* t = upload_table(c, std::vector<const void*>{p});
+    if (t == nullptr && e == hipSuccess) e = hipErrorOutOfMemory;
+    return t;
+  }
   void prog(const Prog& p, const void* in, const void* aux, void* out) {
+    prog_in(p, F64, in, aux, out, MDWF_PROF_DSLASH_F64);
+  }
+  // a program in precision prec on fields of one job
+  void prog_in(const Prog& p, int prec, const void* in, void* out) {
+    prog_in(p, prec, in, nullptr, out, MDWF_PROF_DSLASH_INNER);
+  }
+  void prog_in(const Prog& p, int prec, const void* in, const void* aux, void* out, int cls) {
     if (e != hipSuccess) return;
+    if (coef_d == nullptr) { e = hipErrorInvalidValue; return; }
     char* const* I = tab(in);
     char* const* A = aux ? tab(aux) : nullptr;
     char* const* O = tab(out);
-    e = run_prog(c, g, geom, F64, p, I, A, O, coef_d, 1, nullptr, 0, nullptr, 0, MDWF_PROF_DSLASH_F64,
-                 in != out && aux != out);
+    if (e != hipSuccess) return;
+    e = run_prog(c, g, geom, prec, p, I, A, O, coef_d, 1, nullptr, 0, nullptr, 0, cls, in != out && aux != out);
   }
   void to_half(const void* user, void* half, int par) {
     if (e != hipSuccess) return;
+    char* const* U = tab(user);
+    char* const* H = tab(half);
+    if (e != hipSuccess) return;
     hipEvent_t ev;
     prof_begin(c, &ev);
-    e = layout_user_to_half(geom, tab(user), tab(half), par, F64, 1, c->stream);
+    e = layout_user_to_half(geom, U, H, par, F64, 1, c->stream);
     prof_end(c, MDWF_PROF_OTHER, 0, ev);
   }
   void to_user(const void* half, void* user, int par) {
     if (e != hipSuccess) return;
+    char* const* H = tab(half);
+    char* const* U = tab(user);
+    if (e != hipSuccess) return;
     hipEvent_t ev;
     prof_begin(c, &ev);
-    e = layout_half_to_user(geom, tab(half), tab(user), par, F64, 1, c->stream);
+    e = layout_half_to_user(geom, H, U, par, F64, 1, c->stream);
     prof_end(c, MDWF_PROF_OTHER, 0, ev);
   }
   // out = ca * in + cb * out (precisions pin -> pout)
@@ -163,6 +184,7 @@ struct One {
     B.nslots = 1;
     B.a = tab(in);
     B.b = tab(out);
+    if (e != hipSuccess) return;
     B.ca = ca;
     B.cb = cb;
     hipEvent_t ev;
@@ -339,6 +361,7 @@ extern "C" mdwf_status mdwf_job_begin(mdwf_ctx* c, const mdwf_gauge* g, const md
   for (int r = 0; r < nrhs; ++r) {
     j->fr.push_back(p); p += L.fs;
     j->fp.push_back(p); p += L.fs;
+    j->fpt.push_back(p); p += L.fs;
     j->ft.push_back(p); p += L.fs;
     j->fv.push_back(p); p += L.fs;
     j->fx.push_back(p); p += L.fx;
@@ -391,6 +414,7 @@ extern "C" mdwf_status mdwf_job_begin(mdwf_ctx* c, const mdwf_gauge* g, const md
     if (j->ps != F64) o.zero(j->fx[r], spinor_field_bytes(j->px, geom.L5, geom.Vh));
     o.axpby(T.t1, F64, j->fr[r], j->ps, 1.0, 0.0);      // r = lo(rh)
     o.axpby(j->fr[r], j->ps, j->fp[r], j->ps, 1.0, 0.0);  // p = r
+    o.prog_in(prog_5D(CH_MPHI), j->ps, j->fp[r], j->fpt[r]);
     if (o.e != hipSuccess) { st = hip_err(c, o.e, "job setup"); break; }
     CGState& s = j->st[r];
     s.active = 1;
@@ -454,26 +478,26 @@ extern "C" mdwf_status mdwf_job_step(mdwf_ctx* c, mdwf_job* const* jobs, int32_t
   if (slots.empty() || iters == 0) return MDWF_OK;
 
   using Tab = char* const*;
-  Tab X = nullptr, R = nullptr, P = nullptr, T = nullptr, V = nullptr;
+  Tab X = nullptr, R = nullptr, P = nullptr, PT = nullptr, T = nullptr, V = nullptr;
   const Coef5* coef_d = nullptr;
   CGState* S_d = nullptr;
   double* pd = nullptr;
   double* pb = nullptr;
   auto build = [&]() -> mdwf_status {
     const int n = (int)slots.size();
-    std::vector<const void*> x(n), r(n), p(n), t(n), v(n);
+    std::vector<const void*> x(n), r(n), p(n), pt(n), t(n), v(n);
     std::vector<Coef5> cf(n);
     for (int i = 0; i < n; ++i) {
       mdwf_job* j = slots[i].job;
       const int k = slots[i].r;
-      x[i] = j->fx[k]; r[i] = j->fr[k]; p[i] = j->fp[k];
+      x[i] = j->fx[k]; r[i] = j->fr[k]; p[i] = j->fp[k]; pt[i] = j->fpt[k];
       t[i] = j->ft[k]; v[i] = j->fv[k];
       cf[i] = j->coef;
     }
-    X = upload_table(c, x); R = upload_table(c, r); P = upload_table(c, p);
+    X = upload_table(c, x); R = upload_table(c, r); P = upload_table(c, p); PT = upload_table(c, pt);
     T = upload_table(c, t); V = upload_table(c, v);
     coef_d = static_cast<const Coef5*>(upload_bytes(c, cf.data(), n * sizeof(Coef5)));
-    if (!X || !R || !P || !T || !V || !coef_d) return set_err(c, MDWF_EHIP, "mdwf_job_step: table upload");
+    if (!X || !R || !P || !PT || !T || !V || !coef_d) return set_err(c, MDWF_EHIP, "mdwf_job_step: table upload");
     mdwf_status s2 = ensure(c, c->states, n * sizeof(CGState));
     if (s2 == MDWF_OK) s2 = ensure(c, c->partials_d, (size_t)n * ntiles * sizeof(double));
     if (s2 == MDWF_OK) s2 = ensure(c, c->partials_b, (size_t)n * nblk * sizeof(double));
@@ -509,7 +533,7 @@ extern "C" mdwf_status mdwf_job_step(mdwf_ctx* c, mdwf_job* const* jobs, int32_t
     const int chunk = std::min(remaining, slots[0].job->opts.check_every);
     const int* act = &S_d[0].active;
     for (int it = 0; it < chunk && e == hipSuccess; ++it) {
-      e = run_prog(c, j0->g, geom, ps, prog_A1(), P, nullptr, T, coef_d, n, act, stride, nullptr, 0,
+      e = run_prog(c, j0->g, geom, ps, prog_A1_pt(), PT, nullptr, T, coef_d, n, act, stride, nullptr, 0,
                    MDWF_PROF_DSLASH_INNER, true);
       if (e == hipSuccess)
         e = run_prog(c, j0->g, geom, ps, prog_A2(true, true), T, P, V, coef_d, n, act, stride, pd, ntiles,
@@ -539,11 +563,12 @@ extern "C" mdwf_status mdwf_job_step(mdwf_ctx* c, mdwf_job* const* jobs, int32_t
         BlasArgs B{};
         B.g = geom;
         B.nslots = n;
-        B.a = P; B.b = R;
+        B.a = P; B.b = R; B.c = PT;
         B.st = S_d;
+        B.coef = coef_d;
         prof_begin(c, &ev);
         e = blas_cg_p(B, ps, c->stream);
-        prof_end(c, MDWF_PROF_BLAS, n * ne * 3.0 * spinor_site_bytes(ps), ev);
+        prof_end(c, MDWF_PROF_BLAS, n * ne * 4.0 * spinor_site_bytes(ps), ev);
       }
     }
     if (e != hipSuccess) return hip_err(c, e, "CG iteration");
@@ -588,7 +613,11 @@ extern "C" mdwf_status mdwf_job_step(mdwf_ctx* c, mdwf_job* const* jobs, int32_t
           // continue: beta from the true residual, p = r + beta p
           const double beta = rr / s.rho;
           One o{c, j->g, geom, nullptr};
+          std::vector<Coef5> cf(1, j->coef);
+          o.coef_d = static_cast<const Coef5*>(upload_bytes(c, cf.data(), sizeof(Coef5)));
+          if (o.coef_d == nullptr) return set_err(c, MDWF_EHIP, "reliable update: coefficient upload");
           o.axpby(j->fr[r], ps, j->fp[r], ps, 1.0, beta);
+          o.prog_in(prog_5D(CH_MPHI), ps, j->fp[r], j->fpt[r]);
           if (o.e != hipSuccess) return hip_err(c, o.e, "reliable update");
           s.rho = rr;
           s.rho_new = rr;

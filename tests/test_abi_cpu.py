@@ -65,10 +65,11 @@ def test_job_footprint_model():
     f64 = M.job_footprint(act, M.CGOpts.make(inner="f64"), 1)
     f32 = M.job_footprint(act, M.CGOpts.make(inner="f32"), 12)
     f16 = M.job_footprint(act, M.CGOpts.make(inner="f16"), 12)
-    # FP64: r p t v x (5 fields) + 3 context temporaries
-    assert f64 >= 8 * ne * 192
-    # FP32 per RHS: 4 FP32 work fields + FP32 x + FP64 xh
-    assert f32 >= 12 * (5 * ne * 96 + ne * 192)
+    # FP64: r p M_phi p t v x eta^ (7 fields) + 3 context temporaries
+    assert f64 >= 10 * ne * 192
+    # FP32 per RHS: 5 FP32 work fields (r, p, M_phi p, t, v) + FP32 x + FP64 xh + FP64 eta^
+    assert f32 >= 12 * (6 * ne * 96 + 2 * ne * 192) + 3 * ne * 192
+    assert f32 < 12 * (6 * ne * 96 + 2 * ne * 192) + 3 * ne * 192 + 64 * 1024
     assert f16 < f32
     assert M.job_footprint(act, M.CGOpts.make(inner="f64"), 0) == 0
 
