@@ -1,5 +1,6 @@
 // libmdwf host core: contexts, validation, device memory, pointer tables,
 // profiling, the launch autotuner, gauge fields and sources.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -51,6 +52,15 @@ mdwf_status check_action_msg(const mdwf_action* a, std::string& msg) {
     msg = "lattice too large (V4*L5 must stay below 2^31)";
     return MDWF_EINVAL;
   }
+  {
+    // site coordinates divide checkerboard indices (< V4/2) by Lx/2, Ly, Lz
+    // with 32-bit multiply-high, exact while index * divisor < 2^32
+    const double dmax = std::max({(double)a->L[0] / 2, (double)a->L[1], (double)a->L[2]});
+    if (v4 / 2 * dmax >= 4294967296.0) {
+      msg = "lattice too large (V4/2 * max(Lx/2, Ly, Lz) must stay below 2^32)";
+      return MDWF_EINVAL;
+    }
+  }
   if (a->L5 < 1 || a->L5 > 32) {
     msg = "L5 must be in [1, 32]";
     return MDWF_EINVAL;
@@ -90,6 +100,9 @@ Geom make_geom(const mdwf_action* a) {
   g.Vh = a->L[0] * a->L[1] * a->L[2] * a->L[3] / 2;
   g.L5 = a->L5;
   g.tap = a->t_antiperiodic;
+  g.mLxh = fastdiv_magic((uint32_t)g.Lxh);
+  g.mLy = fastdiv_magic((uint32_t)g.Ly);
+  g.mLz = fastdiv_magic((uint32_t)g.Lz);
   return g;
 }
 

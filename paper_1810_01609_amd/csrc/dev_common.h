@@ -62,16 +62,25 @@ struct Geom {
   int Vh;              // sites per parity
   int L5;
   int tap;             // 1: antiperiodic in t
+  // division by Lxh, Ly, Lz as a multiply-high: q = mulhi(n, m) with
+  // m = floor(2^32 / d) + 1 is exact for n * d < 2^32 (checked when the
+  // action is validated); m = 0 stands for d = 1
+  uint32_t mLxh, mLy, mLz;
 };
+
+__host__ __device__ __forceinline__ uint32_t fastdiv_magic(uint32_t d) {
+  return d <= 1 ? 0u : (uint32_t)((1ull << 32) / d + 1ull);
+}
+__device__ __forceinline__ int fastdiv(int n, uint32_t m) { return m == 0 ? n : (int)__umulhi((uint32_t)n, m); }
 
 // 4D coordinates of the site with checkerboard index cb and parity par.
 __device__ __forceinline__ void site_coords(const Geom& g, int par, int cb, int& x, int& y, int& z, int& t) {
-  const int xh = cb % g.Lxh;
-  int r = cb / g.Lxh;
-  y = r % g.Ly;
-  r /= g.Ly;
-  z = r % g.Lz;
-  t = r / g.Lz;
+  int r = fastdiv(cb, g.mLxh);
+  const int xh = cb - r * g.Lxh;
+  const int r2 = fastdiv(r, g.mLy);
+  y = r - r2 * g.Ly;
+  t = fastdiv(r2, g.mLz);
+  z = r2 - t * g.Lz;
   x = 2 * xh + ((par + y + z + t) & 1);
 }
 
@@ -239,6 +248,8 @@ template <> struct SpinorIO<F32> {
   }
 };
 
+constexpr float kMinNormalF32 = 1.17549435e-38f;
+
 template <int P> struct SpinorIO16 {
   using R = float;
   static __device__ __forceinline__ float scale(const char* base, const FieldDesc& f, int cb, int s) {
@@ -298,7 +309,11 @@ template <int P> struct SpinorIO16 {
     float m = 0.f;
 #pragma unroll
     for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf(v[k]));
-    const float inv = m > 0.f ? 1.0f / m : 0.f;
+    // a site whose largest component is below the smallest normal FP32 value
+    // is stored as zero: 1/m would overflow (and 0 * inf is NaN)
+    const bool keep = m >= kMinNormalF32;
+    const float inv = keep ? 1.0f / m : 0.f;
+    if (!keep) m = 0.f;
     uint4* p = reinterpret_cast<uint4*>(base) + (size_t)s * 3 * f.Vh + cb;
 #pragma unroll
     for (int g = 0; g < 3; ++g) {

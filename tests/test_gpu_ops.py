@@ -115,6 +115,28 @@ def test_op_low_precision(ctx, prec, name, op):
     assert err < TOL[prec], err
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16", "bf16", "i16"])
+@pytest.mark.parametrize("op", ["D", "NORMAL", "MHATDAG", "HOP"])
+def test_op_tiny_sites(ctx, prec, op):
+    """Sites whose magnitude spans 1 down to 1e-60 (far below the FP32
+    range), as at the front of a point-source solve: the per-site scale must
+    neither overflow nor turn the tiny sites into NaN."""
+    from paper_1810_01609_amd import mdwf as M
+
+    U, act, oact, g = _setup(ctx, "c1")
+    x = S.random_spinor(act.lattice, act.L5, 300 + OPS.index(op))
+    rng = np.random.default_rng(17)
+    expo = rng.integers(0, 61, size=x.shape[:5]).astype(np.float64)
+    x = x * (10.0 ** -expo)[..., None, None]
+    expect = _oracle(op, U, x, oact)
+    out = empty_like_dev(x.shape)
+    ctx.dslash(g, act, getattr(M, "OP_" + op), prec, to_dev(x), out)
+    got = to_host(out)
+    assert np.isfinite(got).all()
+    err = rel(got, expect)
+    assert err < TOL[prec], err
+
+
 def test_multi_rhs_dslash_matches_single(ctx):
     from paper_1810_01609_amd import mdwf as M
 
