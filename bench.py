@@ -119,7 +119,8 @@ def serve_bench(args):
         "value": nrhs / wall if ok else 0.0,
         "unit": "solves/s",
         "n_gpus": 1, "steps": len(done), "warmup": 0, "ms_per_step": 1e3 * wall / max(len(done), 1),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": inner, "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if inner == "f64" else "f32",
+        "data": "synthetic",
         "config": {"workload": (f"c5: Poisson stream of {args.requests} requests at {args.rate}/s over volumes "
                                 f"{vols}, L5 in {{8,12,16}}, mq U[0.005,0.05], 1-12 Z2 sources, "
                                 f"chunks of <= {args.max_rhs} RHS, {inner} inner, continuous batching"),
@@ -321,7 +322,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if args.inner == "f64" else "f32",
         "data": "synthetic",
         "config": {
             "workload": (f"{args.workload}: {L[0]}x{L[1]}x{L[2]}x{L[3]} L5={L5} Moebius b5={cfg['b5']} "
