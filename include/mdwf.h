@@ -251,11 +251,15 @@ typedef enum {
   MDWF_PROF_NCLASS = 5
 } mdwf_prof_class;
 
-/* Turn per-launch event timing on (1) or off (0).  Off by default. */
+/* Per-launch kernel timing: on = 0 off (the default), 1 every launch, N > 1
+ * every launch outside the CG iteration loop and the launches of one CG
+ * iteration in N (the others are counted, not timed).  The start and stop
+ * events ride in the kernel dispatches (no marker packets); EINVAL if on < 0. */
 MDWF_API mdwf_status mdwf_profile_enable(mdwf_ctx *ctx, int32_t on);
 MDWF_API mdwf_status mdwf_profile_reset(mdwf_ctx *ctx);
-/* Synchronises the stream, then returns launches, summed kernel time (ms)
- * and summed modelled compulsory bytes for one class. */
+/* Synchronises the stream, then returns, for one class, all launches, the
+ * kernel time in ms (the timed launches' mean times all launches; the plain
+ * sum when every launch is timed) and the summed modelled compulsory bytes. */
 MDWF_API mdwf_status mdwf_profile_read(mdwf_ctx *ctx, int32_t cls, int64_t *launches, double *ms, double *bytes);
 
 /* ---- launch autotuner (paper, "GPU Kernel Autotuning") -------------------- */

@@ -198,11 +198,11 @@ static dim3 blas_grid(BlasArgs& A) {
 hipError_t blas_cg_xr(BlasArgs A, int px, int ps, hipStream_t st) {
   const dim3 grid = blas_grid(A);
   const dim3 blk(kBlasThreads);
-  if (px == F64 && ps == F64) hipLaunchKernelGGL((k_cg_xr<F64, F64>), grid, blk, 0, st, A);
-  else if (px == F32 && ps == F32) hipLaunchKernelGGL((k_cg_xr<F32, F32>), grid, blk, 0, st, A);
-  else if (px == F32 && ps == F16) hipLaunchKernelGGL((k_cg_xr<F32, F16>), grid, blk, 0, st, A);
-  else if (px == F32 && ps == BF16) hipLaunchKernelGGL((k_cg_xr<F32, BF16>), grid, blk, 0, st, A);
-  else if (px == F32 && ps == I16) hipLaunchKernelGGL((k_cg_xr<F32, I16>), grid, blk, 0, st, A);
+  if (px == F64 && ps == F64) launch_k((k_cg_xr<F64, F64>), grid, blk, 0, st, A);
+  else if (px == F32 && ps == F32) launch_k((k_cg_xr<F32, F32>), grid, blk, 0, st, A);
+  else if (px == F32 && ps == F16) launch_k((k_cg_xr<F32, F16>), grid, blk, 0, st, A);
+  else if (px == F32 && ps == BF16) launch_k((k_cg_xr<F32, BF16>), grid, blk, 0, st, A);
+  else if (px == F32 && ps == I16) launch_k((k_cg_xr<F32, I16>), grid, blk, 0, st, A);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -211,11 +211,11 @@ hipError_t blas_cg_p(BlasArgs A, int ps, hipStream_t st) {
   const dim3 grid = blas_grid(A);
   const dim3 blk(kBlasThreads);
   switch (ps) {
-    case F64: hipLaunchKernelGGL(k_cg_p<F64>, grid, blk, 0, st, A); break;
-    case F32: hipLaunchKernelGGL(k_cg_p<F32>, grid, blk, 0, st, A); break;
-    case F16: hipLaunchKernelGGL(k_cg_p<F16>, grid, blk, 0, st, A); break;
-    case BF16: hipLaunchKernelGGL(k_cg_p<BF16>, grid, blk, 0, st, A); break;
-    case I16: hipLaunchKernelGGL(k_cg_p<I16>, grid, blk, 0, st, A); break;
+    case F64: launch_k(k_cg_p<F64>, grid, blk, 0, st, A); break;
+    case F32: launch_k(k_cg_p<F32>, grid, blk, 0, st, A); break;
+    case F16: launch_k(k_cg_p<F16>, grid, blk, 0, st, A); break;
+    case BF16: launch_k(k_cg_p<BF16>, grid, blk, 0, st, A); break;
+    case I16: launch_k(k_cg_p<I16>, grid, blk, 0, st, A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -225,11 +225,11 @@ template <int PI>
 static hipError_t axpby_out(BlasArgs A, int pout, dim3 grid, hipStream_t st) {
   const dim3 blk(kBlasThreads);
   switch (pout) {
-    case F64: hipLaunchKernelGGL((k_axpby<PI, F64>), grid, blk, 0, st, A); break;
-    case F32: hipLaunchKernelGGL((k_axpby<PI, F32>), grid, blk, 0, st, A); break;
-    case F16: hipLaunchKernelGGL((k_axpby<PI, F16>), grid, blk, 0, st, A); break;
-    case BF16: hipLaunchKernelGGL((k_axpby<PI, BF16>), grid, blk, 0, st, A); break;
-    case I16: hipLaunchKernelGGL((k_axpby<PI, I16>), grid, blk, 0, st, A); break;
+    case F64: launch_k((k_axpby<PI, F64>), grid, blk, 0, st, A); break;
+    case F32: launch_k((k_axpby<PI, F32>), grid, blk, 0, st, A); break;
+    case F16: launch_k((k_axpby<PI, F16>), grid, blk, 0, st, A); break;
+    case BF16: launch_k((k_axpby<PI, BF16>), grid, blk, 0, st, A); break;
+    case I16: launch_k((k_axpby<PI, I16>), grid, blk, 0, st, A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -251,11 +251,11 @@ hipError_t blas_norm_diff(BlasArgs A, int p, hipStream_t st) {
   const dim3 grid = blas_grid(A);
   const dim3 blk(kBlasThreads);
   switch (p) {
-    case F64: hipLaunchKernelGGL(k_norm_diff<F64>, grid, blk, 0, st, A); break;
-    case F32: hipLaunchKernelGGL(k_norm_diff<F32>, grid, blk, 0, st, A); break;
-    case F16: hipLaunchKernelGGL(k_norm_diff<F16>, grid, blk, 0, st, A); break;
-    case BF16: hipLaunchKernelGGL(k_norm_diff<BF16>, grid, blk, 0, st, A); break;
-    case I16: hipLaunchKernelGGL(k_norm_diff<I16>, grid, blk, 0, st, A); break;
+    case F64: launch_k(k_norm_diff<F64>, grid, blk, 0, st, A); break;
+    case F32: launch_k(k_norm_diff<F32>, grid, blk, 0, st, A); break;
+    case F16: launch_k(k_norm_diff<F16>, grid, blk, 0, st, A); break;
+    case BF16: launch_k(k_norm_diff<BF16>, grid, blk, 0, st, A); break;
+    case I16: launch_k(k_norm_diff<I16>, grid, blk, 0, st, A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -325,15 +325,15 @@ __global__ __launch_bounds__(kBlasThreads) void k_cg_beta(CGState* S, const doub
 }
 
 hipError_t scalar_reduce(const double* partials, int n, int nslots, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(nslots), dim3(kBlasThreads), 0, st, partials, n, out);
+  launch_k(k_reduce, dim3(nslots), dim3(kBlasThreads), 0, st, partials, n, out);
   return hipGetLastError();
 }
 hipError_t scalar_cg_alpha(CGState* S, const double* partials, int n, int nslots, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_alpha, dim3(nslots), dim3(kBlasThreads), 0, st, S, partials, n);
+  launch_k(k_cg_alpha, dim3(nslots), dim3(kBlasThreads), 0, st, S, partials, n);
   return hipGetLastError();
 }
 hipError_t scalar_cg_beta(CGState* S, const double* partials, int n, int nslots, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_beta, dim3(nslots), dim3(kBlasThreads), 0, st, S, partials, n);
+  launch_k(k_cg_beta, dim3(nslots), dim3(kBlasThreads), 0, st, S, partials, n);
   return hipGetLastError();
 }
 

@@ -195,17 +195,37 @@ static hipEvent_t get_event(mdwf_ctx* c) {
   return e;
 }
 
+LaunchTiming& launch_timing() {
+  static thread_local LaunchTiming t;
+  return t;
+}
+
 void prof_begin(mdwf_ctx* c, hipEvent_t* e0) {
   *e0 = nullptr;
-  if (!c->prof) return;
+  if (!c->prof || c->prof_skip) return;
   *e0 = get_event(c);
-  (void)hipEventRecord(*e0, c->stream);
+  LaunchTiming& t = launch_timing();
+  t.start = *e0;
+  t.stop = get_event(c);
+  t.launches = 0;
 }
 
 void prof_end(mdwf_ctx* c, int cls, double bytes, hipEvent_t e0) {
-  if (!c->prof || e0 == nullptr) return;
-  hipEvent_t e1 = get_event(c);
-  (void)hipEventRecord(e1, c->stream);
+  if (!c->prof) return;
+  if (e0 == nullptr) {  // an iteration that is not sampled: counted, not timed
+    c->prof_launches[cls] += 1;
+    c->prof_bytes[cls] += bytes;
+    return;
+  }
+  LaunchTiming& t = launch_timing();
+  hipEvent_t e1 = t.stop;
+  const int n = t.launches;
+  t = LaunchTiming{};
+  if (n == 0) {  // nothing was launched: no record
+    c->events.push_back(e0);
+    c->events.push_back(e1);
+    return;
+  }
   c->pending.push_back(ProfRec{cls, bytes, e0, e1});
   if (c->pending.size() > 4096) {
     // fold finished records so the pool stays bounded
@@ -214,6 +234,7 @@ void prof_end(mdwf_ctx* c, int cls, double bytes, hipEvent_t e0) {
       float ms = 0;
       (void)hipEventElapsedTime(&ms, r.e0, r.e1);
       c->prof_launches[r.cls] += 1;
+      c->prof_timed[r.cls] += 1;
       c->prof_ms[r.cls] += ms;
       c->prof_bytes[r.cls] += r.bytes;
       c->events.push_back(r.e0);
@@ -582,7 +603,10 @@ mdwf_status mdwf_source_z2(mdwf_ctx* c, const mdwf_action* act, uint64_t seed, i
 
 mdwf_status mdwf_profile_enable(mdwf_ctx* c, int32_t on) {
   if (c == nullptr) return MDWF_EINVAL;
-  c->prof = on != 0;
+  if (on < 0) return set_err(c, MDWF_EINVAL, "mdwf_profile_enable: negative mode");
+  c->prof = on;
+  c->prof_skip = false;
+  c->prof_iter = 0;
   return MDWF_OK;
 }
 
@@ -592,6 +616,7 @@ static void fold_profile(mdwf_ctx* c) {
     float ms = 0;
     (void)hipEventElapsedTime(&ms, r.e0, r.e1);
     c->prof_launches[r.cls] += 1;
+    c->prof_timed[r.cls] += 1;
     c->prof_ms[r.cls] += ms;
     c->prof_bytes[r.cls] += r.bytes;
     c->events.push_back(r.e0);
@@ -605,6 +630,7 @@ mdwf_status mdwf_profile_reset(mdwf_ctx* c) {
   fold_profile(c);
   for (int k = 0; k < MDWF_PROF_NCLASS; ++k) {
     c->prof_launches[k] = 0;
+    c->prof_timed[k] = 0;
     c->prof_ms[k] = 0;
     c->prof_bytes[k] = 0;
   }
@@ -616,7 +642,9 @@ mdwf_status mdwf_profile_read(mdwf_ctx* c, int32_t cls, int64_t* launches, doubl
   if (cls < 0 || cls >= MDWF_PROF_NCLASS) return set_err(c, MDWF_EINVAL, "profile class out of range");
   fold_profile(c);
   if (launches) *launches = c->prof_launches[cls];
-  if (ms) *ms = c->prof_ms[cls];
+  // sampled: the timed launches' mean times every launch of the class
+  const int64_t t = c->prof_timed[cls];
+  if (ms) *ms = t > 0 ? c->prof_ms[cls] * ((double)c->prof_launches[cls] / (double)t) : 0.0;
   if (bytes) *bytes = c->prof_bytes[cls];
   return MDWF_OK;
 }

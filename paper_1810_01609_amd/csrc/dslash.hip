@@ -870,7 +870,7 @@ static hipError_t launch_t(const DslashArgs& A, int threads, size_t smem, int gr
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k, dim3(grid), dim3(threads), smem, st, A);
+  launch_k(k, dim3(grid), dim3(threads), smem, st, A);
   return hipGetLastError();
 }
 

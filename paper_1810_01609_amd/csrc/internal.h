@@ -41,10 +41,13 @@ struct mdwf_ctx {
   bool own_stream = false;
   std::string err;
   // profiling
-  bool prof = false;
+  int prof = 0;            // 0 off, 1 every launch, N > 1 one CG iteration in N
+  bool prof_skip = false;  // inside a CG iteration that is not sampled
+  int64_t prof_iter = 0;   // CG iterations seen while sampling
   std::vector<mdwf::ProfRec> pending;
   std::vector<hipEvent_t> events;
   int64_t prof_launches[MDWF_PROF_NCLASS] = {};
+  int64_t prof_timed[MDWF_PROF_NCLASS] = {};
   double prof_ms[MDWF_PROF_NCLASS] = {};
   double prof_bytes[MDWF_PROF_NCLASS] = {};
   // autotuner: key -> log2 of sites per workgroup

@@ -1,6 +1,7 @@
 // Launch interface of the libmdwf HIP kernels (internal to the library).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -8,6 +9,25 @@
 #include "dev_common.h"
 
 namespace mdwf {
+
+// Kernel-time profiling without marker packets: while a profiled library
+// call is in flight on this thread, the first kernel it launches carries the
+// start event and every kernel it launches records the stop event, both
+// inside the dispatch itself.
+struct LaunchTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+  int launches = 0;
+};
+LaunchTiming& launch_timing();
+
+template <class F, class... Args>
+inline hipError_t launch_k(F kernel, dim3 grid, dim3 block, size_t smem, hipStream_t st, Args... args) {
+  LaunchTiming& t = launch_timing();
+  hipEvent_t e0 = (t.stop != nullptr && t.launches == 0) ? t.start : nullptr;
+  hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)smem, st, e0, t.stop, 0u, args...);
+  if (t.stop != nullptr) ++t.launches;
+  return hipGetLastError();
+}
 
 // Fifth-dimension chains applied to whole columns of a site.
 enum Chain : int {

@@ -128,11 +128,11 @@ hipError_t layout_user_to_half(const Geom& g, const char* const* user, char* con
                                int nslots, hipStream_t st) {
   const dim3 grid((g.Vh + 255) / 256, g.L5, nslots), blk(256);
   switch (p) {
-    case F64: hipLaunchKernelGGL(k_user_to_half<F64>, grid, blk, 0, st, g, user, half, par); break;
-    case F32: hipLaunchKernelGGL(k_user_to_half<F32>, grid, blk, 0, st, g, user, half, par); break;
-    case F16: hipLaunchKernelGGL(k_user_to_half<F16>, grid, blk, 0, st, g, user, half, par); break;
-    case BF16: hipLaunchKernelGGL(k_user_to_half<BF16>, grid, blk, 0, st, g, user, half, par); break;
-    case I16: hipLaunchKernelGGL(k_user_to_half<I16>, grid, blk, 0, st, g, user, half, par); break;
+    case F64: launch_k(k_user_to_half<F64>, grid, blk, 0, st, g, user, half, par); break;
+    case F32: launch_k(k_user_to_half<F32>, grid, blk, 0, st, g, user, half, par); break;
+    case F16: launch_k(k_user_to_half<F16>, grid, blk, 0, st, g, user, half, par); break;
+    case BF16: launch_k(k_user_to_half<BF16>, grid, blk, 0, st, g, user, half, par); break;
+    case I16: launch_k(k_user_to_half<I16>, grid, blk, 0, st, g, user, half, par); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -142,11 +142,11 @@ hipError_t layout_half_to_user(const Geom& g, const char* const* half, char* con
                                int nslots, hipStream_t st) {
   const dim3 grid((g.Vh + 255) / 256, g.L5, nslots), blk(256);
   switch (p) {
-    case F64: hipLaunchKernelGGL(k_half_to_user<F64>, grid, blk, 0, st, g, half, user, par); break;
-    case F32: hipLaunchKernelGGL(k_half_to_user<F32>, grid, blk, 0, st, g, half, user, par); break;
-    case F16: hipLaunchKernelGGL(k_half_to_user<F16>, grid, blk, 0, st, g, half, user, par); break;
-    case BF16: hipLaunchKernelGGL(k_half_to_user<BF16>, grid, blk, 0, st, g, half, user, par); break;
-    case I16: hipLaunchKernelGGL(k_half_to_user<I16>, grid, blk, 0, st, g, half, user, par); break;
+    case F64: launch_k(k_half_to_user<F64>, grid, blk, 0, st, g, half, user, par); break;
+    case F32: launch_k(k_half_to_user<F32>, grid, blk, 0, st, g, half, user, par); break;
+    case F16: launch_k(k_half_to_user<F16>, grid, blk, 0, st, g, half, user, par); break;
+    case BF16: launch_k(k_half_to_user<BF16>, grid, blk, 0, st, g, half, user, par); break;
+    case I16: launch_k(k_half_to_user<I16>, grid, blk, 0, st, g, half, user, par); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -155,11 +155,11 @@ hipError_t layout_half_to_user(const Geom& g, const char* const* half, char* con
 hipError_t layout_gauge(const Geom& g, const double* user, char* out, int p, hipStream_t st) {
   const dim3 grid((g.Vh + 255) / 256, 4, 2), blk(256);
   switch (p) {
-    case F64: hipLaunchKernelGGL(k_gauge<F64>, grid, blk, 0, st, g, user, out); break;
-    case F32: hipLaunchKernelGGL(k_gauge<F32>, grid, blk, 0, st, g, user, out); break;
-    case F16: hipLaunchKernelGGL(k_gauge<F16>, grid, blk, 0, st, g, user, out); break;
-    case BF16: hipLaunchKernelGGL(k_gauge<BF16>, grid, blk, 0, st, g, user, out); break;
-    case I16: hipLaunchKernelGGL(k_gauge<I16>, grid, blk, 0, st, g, user, out); break;
+    case F64: launch_k(k_gauge<F64>, grid, blk, 0, st, g, user, out); break;
+    case F32: launch_k(k_gauge<F32>, grid, blk, 0, st, g, user, out); break;
+    case F16: launch_k(k_gauge<F16>, grid, blk, 0, st, g, user, out); break;
+    case BF16: launch_k(k_gauge<BF16>, grid, blk, 0, st, g, user, out); break;
+    case I16: launch_k(k_gauge<I16>, grid, blk, 0, st, g, user, out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -170,11 +170,11 @@ hipError_t fill_zero(void* ptr, size_t bytes, hipStream_t st) {
   if (n16 > 0) {
     size_t blocks = (n16 + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<uint4*>(ptr), n16);
+    launch_k(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<uint4*>(ptr), n16);
   }
   const size_t tail = bytes - n16 * 16;
   if (tail > 0)
-    hipLaunchKernelGGL(k_fill_zero_tail, dim3(1), dim3(16), 0, st,
+    launch_k(k_fill_zero_tail, dim3(1), dim3(16), 0, st,
                        reinterpret_cast<unsigned char*>(ptr) + n16 * 16, tail);
   return hipGetLastError();
 }
@@ -183,7 +183,7 @@ hipError_t source_point(const Geom& g, double* eta, const int x0[4], int spin, i
   const size_t bytes = (size_t)g.Vh * 2 * g.L5 * 12 * 16;
   hipError_t e = fill_zero(eta, bytes, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_source_point, dim3(1), dim3(64), 0, st, g, eta, x0[0], x0[1], x0[2], x0[3], spin, colour);
+  launch_k(k_source_point, dim3(1), dim3(64), 0, st, g, eta, x0[0], x0[1], x0[2], x0[3], spin, colour);
   return hipGetLastError();
 }
 
@@ -193,7 +193,7 @@ hipError_t source_z2(const Geom& g, double* eta, uint64_t seed, int rhs_index, h
   hipError_t e = fill_zero(eta, bytes, st);
   if (e != hipSuccess) return e;
   const size_t n = V4 * 12;
-  hipLaunchKernelGGL(k_source_z2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, eta, seed, rhs_index);
+  launch_k(k_source_z2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, eta, seed, rhs_index);
   return hipGetLastError();
 }
 

@@ -275,8 +275,10 @@ class Context:
         return lib().mdwf_job_step(self._h, arr, len(jobs), int(iters))
 
     # ---- measurement ----
-    def profile_enable(self, on=True):
-        self._check(lib().mdwf_profile_enable(self._h, 1 if on else 0), "mdwf_profile_enable")
+    def profile_enable(self, on=True, sample: int = 1):
+        """Kernel timing on/off; sample = N > 1 times one CG iteration in N."""
+        mode = 0 if not on else max(int(sample), 1)
+        self._check(lib().mdwf_profile_enable(self._h, mode), "mdwf_profile_enable")
 
     def profile_reset(self):
         self._check(lib().mdwf_profile_reset(self._h), "mdwf_profile_reset")
