@@ -258,8 +258,10 @@ typedef enum {
 MDWF_API mdwf_status mdwf_profile_enable(mdwf_ctx *ctx, int32_t on);
 MDWF_API mdwf_status mdwf_profile_reset(mdwf_ctx *ctx);
 /* Synchronises the stream, then returns, for one class, all launches, the
- * kernel time in ms (the timed launches' mean times all launches; the plain
- * sum when every launch is timed) and the summed modelled compulsory bytes. */
+ * kernel time in ms and the summed modelled compulsory bytes.  The time is
+ * the plain sum when every launch is timed; when sampling, launches inside
+ * and outside the CG loop are kept apart and each group's timed mean is
+ * multiplied by that group's launch count. */
 MDWF_API mdwf_status mdwf_profile_read(mdwf_ctx *ctx, int32_t cls, int64_t *launches, double *ms, double *bytes);
 
 /* ---- launch autotuner (paper, "GPU Kernel Autotuning") -------------------- */

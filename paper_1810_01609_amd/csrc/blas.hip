@@ -32,43 +32,6 @@ __device__ __forceinline__ double block_sum_256(double v) {
   return t;
 }
 
-template <int PX, int PS>
-__global__ __launch_bounds__(kBlasThreads) void k_cg_xr(BlasArgs A) {
-  using RX = typename PrecTraits<PX>::Real;
-  using RS = typename PrecTraits<PS>::Real;
-  const int slot = blockIdx.y;
-  const CGState& S = A.st[slot];
-  if (!S.active) return;
-  const int cb = blockIdx.x * kBlasThreads + threadIdx.x;
-  const FieldDesc f{A.g.Vh, A.g.L5};
-  const double alpha = S.alpha;
-  double loc = 0;
-  if (cb < A.g.Vh) {
-    char* x = A.a[slot];
-    const char* p = A.b[slot];
-    char* r = A.c[slot];
-    const char* q = A.d[slot];
-    for (int s = 0; s < A.g.L5; ++s) {
-      RS pv[24], qv[24], rv[24];
-      RX xv[24];
-      SpinorIO<PS>::load(p, f, cb, s, pv);
-      SpinorIO<PS>::load(q, f, cb, s, qv);
-      SpinorIO<PS>::load(r, f, cb, s, rv);
-      SpinorIO<PX>::load(x, f, cb, s, xv);
-#pragma unroll
-      for (int k = 0; k < 24; ++k) {
-        xv[k] += (RX)alpha * (RX)pv[k];
-        rv[k] -= (RS)alpha * qv[k];
-        loc += (double)rv[k] * (double)rv[k];
-      }
-      SpinorIO<PX>::store(x, f, cb, s, xv);
-      SpinorIO<PS>::store(r, f, cb, s, rv);
-    }
-  }
-  const double t = block_sum_256(loc);
-  if (threadIdx.x == 0) A.partials[(size_t)slot * A.nblk + blockIdx.x] = t;
-}
-
 // p = r + beta p on every slice of a 4D site, and pt = M_phi p from the
 // new p: (M_phi p)_s = b5 p_s + c5 (P5 p)_s, P5 taking spins 0,1 from slice
 // s - 1 and spins 2,3 from slice s + 1, the wall hop carrying -mq.  pt is the
@@ -195,17 +158,6 @@ static dim3 blas_grid(BlasArgs& A) {
   return dim3(A.nblk, A.nslots);
 }
 
-hipError_t blas_cg_xr(BlasArgs A, int px, int ps, hipStream_t st) {
-  const dim3 grid = blas_grid(A);
-  const dim3 blk(kBlasThreads);
-  if (px == F64 && ps == F64) launch_k((k_cg_xr<F64, F64>), grid, blk, 0, st, A);
-  else if (px == F32 && ps == F32) launch_k((k_cg_xr<F32, F32>), grid, blk, 0, st, A);
-  else if (px == F32 && ps == F16) launch_k((k_cg_xr<F32, F16>), grid, blk, 0, st, A);
-  else if (px == F32 && ps == BF16) launch_k((k_cg_xr<F32, BF16>), grid, blk, 0, st, A);
-  else if (px == F32 && ps == I16) launch_k((k_cg_xr<F32, I16>), grid, blk, 0, st, A);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
-}
 
 hipError_t blas_cg_p(BlasArgs A, int ps, hipStream_t st) {
   const dim3 grid = blas_grid(A);
@@ -262,22 +214,49 @@ hipError_t blas_norm_diff(BlasArgs A, int p, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// scalar kernels: one 256-thread workgroup per right-hand side
+// scalar kernels: one 1024-thread workgroup per right-hand side
 // ---------------------------------------------------------------------------
+constexpr int kScalarThreads = 1024;
+
+// Sum of one slot's n partials in a fixed order (four independent strided
+// accumulators per thread, then a fixed tree); valid in thread 0.
 __device__ __forceinline__ double slot_sum(const double* partials, int n, int slot) {
-  double v = 0;
-  for (int j = threadIdx.x; j < n; j += kBlasThreads) v += partials[(size_t)slot * n + j];
-  return block_sum_256(v);
+  const double* q = partials + (size_t)slot * n;
+  constexpr int T = kScalarThreads;
+  double v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+  int j = threadIdx.x;
+  for (; j + 3 * T < n; j += 4 * T) {
+    v0 += q[j];
+    v1 += q[j + T];
+    v2 += q[j + 2 * T];
+    v3 += q[j + 3 * T];
+  }
+  for (; j < n; j += T) v0 += q[j];
+  double v = (v0 + v1) + (v2 + v3);
+  __shared__ double red[T / 64];
+  v += __shfl_xor(v, 32);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 8);
+  v += __shfl_xor(v, 4);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < T / 64; ++w) t += red[w];
+  return t;
 }
 
-__global__ __launch_bounds__(kBlasThreads) void k_reduce(const double* partials, int n, double* out) {
+__global__ __launch_bounds__(kScalarThreads) void k_reduce(const double* partials, int n, double* out) {
   const double t = slot_sum(partials, n, blockIdx.x);
   if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
 __device__ __forceinline__ bool finite_d(double v) { return v == v && v - v == 0.0; }
 
-__global__ __launch_bounds__(kBlasThreads) void k_cg_alpha(CGState* S, const double* partials, int n) {
+__global__ __launch_bounds__(kScalarThreads) void k_cg_alpha(CGState* S, const double* partials, int n) {
   const int slot = blockIdx.x;
   if (!S[slot].active) return;
   const double pq = slot_sum(partials, n, slot);
@@ -296,7 +275,7 @@ __global__ __launch_bounds__(kBlasThreads) void k_cg_alpha(CGState* S, const dou
   }
 }
 
-__global__ __launch_bounds__(kBlasThreads) void k_cg_beta(CGState* S, const double* partials, int n) {
+__global__ __launch_bounds__(kScalarThreads) void k_cg_beta(CGState* S, const double* partials, int n) {
   const int slot = blockIdx.x;
   if (!S[slot].active) return;
   const double rr = slot_sum(partials, n, slot);
@@ -325,15 +304,15 @@ __global__ __launch_bounds__(kBlasThreads) void k_cg_beta(CGState* S, const doub
 }
 
 hipError_t scalar_reduce(const double* partials, int n, int nslots, double* out, hipStream_t st) {
-  launch_k(k_reduce, dim3(nslots), dim3(kBlasThreads), 0, st, partials, n, out);
+  launch_k(k_reduce, dim3(nslots), dim3(kScalarThreads), 0, st, partials, n, out);
   return hipGetLastError();
 }
 hipError_t scalar_cg_alpha(CGState* S, const double* partials, int n, int nslots, hipStream_t st) {
-  launch_k(k_cg_alpha, dim3(nslots), dim3(kBlasThreads), 0, st, S, partials, n);
+  launch_k(k_cg_alpha, dim3(nslots), dim3(kScalarThreads), 0, st, S, partials, n);
   return hipGetLastError();
 }
 hipError_t scalar_cg_beta(CGState* S, const double* partials, int n, int nslots, hipStream_t st) {
-  launch_k(k_cg_beta, dim3(nslots), dim3(kBlasThreads), 0, st, S, partials, n);
+  launch_k(k_cg_beta, dim3(nslots), dim3(kScalarThreads), 0, st, S, partials, n);
   return hipGetLastError();
 }
 

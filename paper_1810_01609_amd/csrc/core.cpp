@@ -212,9 +212,10 @@ void prof_begin(mdwf_ctx* c, hipEvent_t* e0) {
 
 void prof_end(mdwf_ctx* c, int cls, double bytes, hipEvent_t e0) {
   if (!c->prof) return;
+  const int sr = c->prof_loop ? 1 : 0;
   if (e0 == nullptr) {  // an iteration that is not sampled: counted, not timed
-    c->prof_launches[cls] += 1;
-    c->prof_bytes[cls] += bytes;
+    c->prof_launches[cls][sr] += 1;
+    c->prof_bytes[cls][sr] += bytes;
     return;
   }
   LaunchTiming& t = launch_timing();
@@ -226,17 +227,17 @@ void prof_end(mdwf_ctx* c, int cls, double bytes, hipEvent_t e0) {
     c->events.push_back(e1);
     return;
   }
-  c->pending.push_back(ProfRec{cls, bytes, e0, e1});
+  c->pending.push_back(ProfRec{cls, sr, bytes, e0, e1});
   if (c->pending.size() > 4096) {
     // fold finished records so the pool stays bounded
     (void)hipEventSynchronize(e1);
     for (auto& r : c->pending) {
       float ms = 0;
       (void)hipEventElapsedTime(&ms, r.e0, r.e1);
-      c->prof_launches[r.cls] += 1;
-      c->prof_timed[r.cls] += 1;
-      c->prof_ms[r.cls] += ms;
-      c->prof_bytes[r.cls] += r.bytes;
+      c->prof_launches[r.cls][r.stratum] += 1;
+      c->prof_timed[r.cls][r.stratum] += 1;
+      c->prof_ms[r.cls][r.stratum] += ms;
+      c->prof_bytes[r.cls][r.stratum] += r.bytes;
       c->events.push_back(r.e0);
       c->events.push_back(r.e1);
     }
@@ -606,6 +607,7 @@ mdwf_status mdwf_profile_enable(mdwf_ctx* c, int32_t on) {
   if (on < 0) return set_err(c, MDWF_EINVAL, "mdwf_profile_enable: negative mode");
   c->prof = on;
   c->prof_skip = false;
+  c->prof_loop = false;
   c->prof_iter = 0;
   return MDWF_OK;
 }
@@ -615,10 +617,10 @@ static void fold_profile(mdwf_ctx* c) {
   for (auto& r : c->pending) {
     float ms = 0;
     (void)hipEventElapsedTime(&ms, r.e0, r.e1);
-    c->prof_launches[r.cls] += 1;
-    c->prof_timed[r.cls] += 1;
-    c->prof_ms[r.cls] += ms;
-    c->prof_bytes[r.cls] += r.bytes;
+    c->prof_launches[r.cls][r.stratum] += 1;
+    c->prof_timed[r.cls][r.stratum] += 1;
+    c->prof_ms[r.cls][r.stratum] += ms;
+    c->prof_bytes[r.cls][r.stratum] += r.bytes;
     c->events.push_back(r.e0);
     c->events.push_back(r.e1);
   }
@@ -628,12 +630,13 @@ static void fold_profile(mdwf_ctx* c) {
 mdwf_status mdwf_profile_reset(mdwf_ctx* c) {
   if (c == nullptr) return MDWF_EINVAL;
   fold_profile(c);
-  for (int k = 0; k < MDWF_PROF_NCLASS; ++k) {
-    c->prof_launches[k] = 0;
-    c->prof_timed[k] = 0;
-    c->prof_ms[k] = 0;
-    c->prof_bytes[k] = 0;
-  }
+  for (int k = 0; k < MDWF_PROF_NCLASS; ++k)
+    for (int sr = 0; sr < 2; ++sr) {
+      c->prof_launches[k][sr] = 0;
+      c->prof_timed[k][sr] = 0;
+      c->prof_ms[k][sr] = 0;
+      c->prof_bytes[k][sr] = 0;
+    }
   return MDWF_OK;
 }
 
@@ -641,11 +644,19 @@ mdwf_status mdwf_profile_read(mdwf_ctx* c, int32_t cls, int64_t* launches, doubl
   if (c == nullptr) return MDWF_EINVAL;
   if (cls < 0 || cls >= MDWF_PROF_NCLASS) return set_err(c, MDWF_EINVAL, "profile class out of range");
   fold_profile(c);
-  if (launches) *launches = c->prof_launches[cls];
-  // sampled: the timed launches' mean times every launch of the class
-  const int64_t t = c->prof_timed[cls];
-  if (ms) *ms = t > 0 ? c->prof_ms[cls] * ((double)c->prof_launches[cls] / (double)t) : 0.0;
-  if (bytes) *bytes = c->prof_bytes[cls];
+  // per stratum, the timed launches' mean times the stratum's launches (the
+  // plain sum where every launch was timed)
+  int64_t n = 0;
+  double t_ms = 0, b = 0;
+  for (int sr = 0; sr < 2; ++sr) {
+    const int64_t t = c->prof_timed[cls][sr];
+    n += c->prof_launches[cls][sr];
+    b += c->prof_bytes[cls][sr];
+    if (t > 0) t_ms += c->prof_ms[cls][sr] * ((double)c->prof_launches[cls][sr] / (double)t);
+  }
+  if (launches) *launches = n;
+  if (ms) *ms = t_ms;
+  if (bytes) *bytes = b;
   return MDWF_OK;
 }
 

@@ -32,14 +32,30 @@ template <> struct PrecTraits<I16> { using Real = float; };
 
 __host__ __device__ __forceinline__ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Spinor fields are stored in tiles of kSiteTile consecutive sites: a tile
+// holds all L5 slices and all 16-byte groups of its sites, site fastest
+// ([tile][s][group][site in tile]), so a workgroup's slice columns and the
+// x/y neighbours of its sites sit in a few contiguous pages instead of one
+// page per (slice, group) stream.
+constexpr int kSiteTile = 64;
+__host__ __device__ __forceinline__ size_t padded_vh(int Vh) { return round_up((size_t)Vh, kSiteTile); }
+// index, in 16-byte units, of group g of slice s of site cb (G groups per site)
+__host__ __device__ __forceinline__ size_t tile_index(int cb, int s, int g, int L5, int G) {
+  return ((size_t)(cb / kSiteTile) * L5 + s) * (size_t)(G * kSiteTile) + (size_t)g * kSiteTile + (cb % kSiteTile);
+}
+// index of the per-site scale of (cb, s) in the 16-bit scale array
+__host__ __device__ __forceinline__ size_t tile_scale_index(int cb, int s, int L5) {
+  return ((size_t)(cb / kSiteTile) * L5 + s) * kSiteTile + (cb % kSiteTile);
+}
+
 // Byte offset of the per-site scale array inside a 16-bit spinor field.
 __host__ __device__ __forceinline__ size_t half_scale_offset(int L5, int Vh) {
-  return round_up((size_t)L5 * (size_t)Vh * 48u, 256u);
+  return round_up((size_t)L5 * padded_vh(Vh) * 48u, 256u);
 }
 
 // Bytes of one spinor half-field of precision p.
 __host__ __device__ __forceinline__ size_t spinor_field_bytes(int p, int L5, int Vh) {
-  const size_t n = (size_t)L5 * (size_t)Vh;
+  const size_t n = (size_t)L5 * padded_vh(Vh);
   switch (p) {
     case F64: return n * 192u;
     case F32: return n * 96u;
@@ -53,7 +69,15 @@ __host__ __device__ __forceinline__ int link_real_bytes(int p) { return p == F64
 
 // Bytes of one gauge field (both parities, 4 directions, 12 reals per link).
 __host__ __device__ __forceinline__ size_t gauge_field_bytes(int p, int Vh) {
-  return (size_t)2 * 4 * 12 * (size_t)Vh * link_real_bytes(p);
+  return (size_t)2 * 4 * 12 * padded_vh(Vh) * link_real_bytes(p);
+}
+
+// Links are tiled like spinors: [parity][tile][mu][group][site in tile], G
+// groups of 16 (FP64, FP32) or 8 (16-bit) bytes per link; index in groups.
+__host__ __device__ __forceinline__ size_t link_index(int par, int mu, int g, int cb, int Vh, int G) {
+  const size_t ntile = padded_vh(Vh) / kSiteTile;
+  return (((size_t)par * ntile + cb / kSiteTile) * 4 + mu) * (size_t)(G * kSiteTile) + (size_t)g * kSiteTile +
+         (cb % kSiteTile);
 }
 
 struct Geom {
@@ -192,38 +216,38 @@ template <int P> struct SpinorIO;
 template <> struct SpinorIO<F64> {
   using R = double;
   static __device__ __forceinline__ void load(const char* base, const FieldDesc& f, int cb, int s, R v[24]) {
-    const double2* p = reinterpret_cast<const double2*>(base) + (size_t)s * 12 * f.Vh + cb;
+    const double2* p = reinterpret_cast<const double2*>(base) + tile_index(cb, s, 0, f.L5, 12);
 #pragma unroll
     for (int g = 0; g < 12; ++g) {
-      const v2d d = ldg<v2d>(p + (size_t)g * f.Vh);
+      const v2d d = ldg<v2d>(p + (size_t)g * kSiteTile);
       v[2 * g] = d.x;
       v[2 * g + 1] = d.y;
     }
   }
   // h = 0: comps 0..5 (spins 0,1); h = 1: comps 6..11 (spins 2,3)
   static __device__ __forceinline__ void load_half(const char* base, const FieldDesc& f, int cb, int s, int h, R v[12]) {
-    const double2* p = reinterpret_cast<const double2*>(base) + ((size_t)s * 12 + 6 * h) * f.Vh + cb;
+    const double2* p = reinterpret_cast<const double2*>(base) + tile_index(cb, s, 6 * h, f.L5, 12);
 #pragma unroll
     for (int g = 0; g < 6; ++g) {
-      const v2d d = ldg<v2d>(p + (size_t)g * f.Vh);
+      const v2d d = ldg<v2d>(p + (size_t)g * kSiteTile);
       v[2 * g] = d.x;
       v[2 * g + 1] = d.y;
     }
   }
   static __device__ __forceinline__ void store(char* base, const FieldDesc& f, int cb, int s, const R v[24]) {
-    double2* p = reinterpret_cast<double2*>(base) + (size_t)s * 12 * f.Vh + cb;
+    double2* p = reinterpret_cast<double2*>(base) + tile_index(cb, s, 0, f.L5, 12);
 #pragma unroll
-    for (int g = 0; g < 12; ++g) stg<v2d>(p + (size_t)g * f.Vh, v2d{v[2 * g], v[2 * g + 1]});
+    for (int g = 0; g < 12; ++g) stg<v2d>(p + (size_t)g * kSiteTile, v2d{v[2 * g], v[2 * g + 1]});
   }
 };
 
 template <> struct SpinorIO<F32> {
   using R = float;
   static __device__ __forceinline__ void load(const char* base, const FieldDesc& f, int cb, int s, R v[24]) {
-    const float4* p = reinterpret_cast<const float4*>(base) + (size_t)s * 6 * f.Vh + cb;
+    const float4* p = reinterpret_cast<const float4*>(base) + tile_index(cb, s, 0, f.L5, 6);
 #pragma unroll
     for (int g = 0; g < 6; ++g) {
-      const v4f d = ldg<v4f>(p + (size_t)g * f.Vh);
+      const v4f d = ldg<v4f>(p + (size_t)g * kSiteTile);
       v[4 * g] = d.x;
       v[4 * g + 1] = d.y;
       v[4 * g + 2] = d.z;
@@ -231,10 +255,10 @@ template <> struct SpinorIO<F32> {
     }
   }
   static __device__ __forceinline__ void load_half(const char* base, const FieldDesc& f, int cb, int s, int h, R v[12]) {
-    const float4* p = reinterpret_cast<const float4*>(base) + ((size_t)s * 6 + 3 * h) * f.Vh + cb;
+    const float4* p = reinterpret_cast<const float4*>(base) + tile_index(cb, s, 3 * h, f.L5, 6);
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
-      const v4f d = ldg<v4f>(p + (size_t)g * f.Vh);
+      const v4f d = ldg<v4f>(p + (size_t)g * kSiteTile);
       v[4 * g] = d.x;
       v[4 * g + 1] = d.y;
       v[4 * g + 2] = d.z;
@@ -242,9 +266,9 @@ template <> struct SpinorIO<F32> {
     }
   }
   static __device__ __forceinline__ void store(char* base, const FieldDesc& f, int cb, int s, const R v[24]) {
-    float4* p = reinterpret_cast<float4*>(base) + (size_t)s * 6 * f.Vh + cb;
+    float4* p = reinterpret_cast<float4*>(base) + tile_index(cb, s, 0, f.L5, 6);
 #pragma unroll
-    for (int g = 0; g < 6; ++g) stg<v4f>(p + (size_t)g * f.Vh, v4f{v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]});
+    for (int g = 0; g < 6; ++g) stg<v4f>(p + (size_t)g * kSiteTile, v4f{v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]});
   }
 };
 
@@ -253,10 +277,10 @@ constexpr float kMinNormalF32 = 1.17549435e-38f;
 template <int P> struct SpinorIO16 {
   using R = float;
   static __device__ __forceinline__ float scale(const char* base, const FieldDesc& f, int cb, int s) {
-    return ldg<float>(reinterpret_cast<const float*>(base + half_scale_offset(f.L5, f.Vh)) + (size_t)s * f.Vh + cb);
+    return ldg<float>(reinterpret_cast<const float*>(base + half_scale_offset(f.L5, f.Vh)) + tile_scale_index(cb, s, f.L5));
   }
   static __device__ __forceinline__ void group(const char* base, const FieldDesc& f, int cb, int s, int g, float sc, R* v) {
-    const v4u q = ldg<v4u>(reinterpret_cast<const uint4*>(base) + ((size_t)s * 3 + g) * f.Vh + cb);
+    const v4u q = ldg<v4u>(reinterpret_cast<const uint4*>(base) + tile_index(cb, s, g, f.L5, 3));
     const uint32_t w[4] = {q.x, q.y, q.z, q.w};
     if constexpr (P == I16) {
       // q/32767 * sc as q * (sc/32767): one multiply per value
@@ -284,7 +308,7 @@ template <int P> struct SpinorIO16 {
     sc = scale(base, f, cb, s);
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
-      const v4u d = ldg<v4u>(reinterpret_cast<const uint4*>(base) + ((size_t)s * 3 + g) * f.Vh + cb);
+      const v4u d = ldg<v4u>(reinterpret_cast<const uint4*>(base) + tile_index(cb, s, g, f.L5, 3));
       q[4 * g] = d.x;
       q[4 * g + 1] = d.y;
       q[4 * g + 2] = d.z;
@@ -314,15 +338,15 @@ template <int P> struct SpinorIO16 {
     const bool keep = m >= kMinNormalF32;
     const float inv = keep ? 1.0f / m : 0.f;
     if (!keep) m = 0.f;
-    uint4* p = reinterpret_cast<uint4*>(base) + (size_t)s * 3 * f.Vh + cb;
+    uint4* p = reinterpret_cast<uint4*>(base) + tile_index(cb, s, 0, f.L5, 3);
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
       const R* w = v + 8 * g;
       const v4u q{pack2<P>(w[0] * inv, w[1] * inv), pack2<P>(w[2] * inv, w[3] * inv),
                   pack2<P>(w[4] * inv, w[5] * inv), pack2<P>(w[6] * inv, w[7] * inv)};
-      stg<v4u>(p + (size_t)g * f.Vh, q);
+      stg<v4u>(p + (size_t)g * kSiteTile, q);
     }
-    stg<float>(reinterpret_cast<float*>(base + half_scale_offset(f.L5, f.Vh)) + (size_t)s * f.Vh + cb, m);
+    stg<float>(reinterpret_cast<float*>(base + half_scale_offset(f.L5, f.Vh)) + tile_scale_index(cb, s, f.L5), m);
   }
 };
 template <> struct SpinorIO<F16> : SpinorIO16<F16> {};
@@ -355,19 +379,19 @@ template <int P> struct LinkIO;
 template <> struct LinkIO<F64> {
   using R = double;
   static __device__ __forceinline__ void load_raw(const char* gbase, int Vh, int par, int mu, int cb, R r[12]) {
-    const double2* p = reinterpret_cast<const double2*>(gbase) + (size_t)((par * 4 + mu) * 6) * Vh + cb;
+    const double2* p = reinterpret_cast<const double2*>(gbase) + link_index(par, mu, 0, cb, Vh, 6);
 #pragma unroll
     for (int g = 0; g < 6; ++g) {
-      const v2d d = ldg<v2d>(p + (size_t)g * Vh);
+      const v2d d = ldg<v2d>(p + (size_t)g * kSiteTile);
       r[2 * g] = d.x;
       r[2 * g + 1] = d.y;
     }
   }
   static __device__ __forceinline__ void load(const char* gbase, int Vh, int par, int mu, int cb, Cplx<R> U[3][3]) {
-    const double2* p = reinterpret_cast<const double2*>(gbase) + (size_t)((par * 4 + mu) * 6) * Vh + cb;
+    const double2* p = reinterpret_cast<const double2*>(gbase) + link_index(par, mu, 0, cb, Vh, 6);
 #pragma unroll
     for (int g = 0; g < 6; ++g) {
-      const v2d d = ldg<v2d>(p + (size_t)g * Vh);
+      const v2d d = ldg<v2d>(p + (size_t)g * kSiteTile);
       U[g / 3][g % 3] = {d.x, d.y};
     }
     reconstruct_row2(U);
@@ -377,19 +401,19 @@ template <> struct LinkIO<F64> {
 template <> struct LinkIO<F32> {
   using R = float;
   static __device__ __forceinline__ void load_raw(const char* gbase, int Vh, int par, int mu, int cb, R r[12]) {
-    const float4* p = reinterpret_cast<const float4*>(gbase) + (size_t)((par * 4 + mu) * 3) * Vh + cb;
+    const float4* p = reinterpret_cast<const float4*>(gbase) + link_index(par, mu, 0, cb, Vh, 3);
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
-      const v4f d = ldg<v4f>(p + (size_t)g * Vh);
+      const v4f d = ldg<v4f>(p + (size_t)g * kSiteTile);
       r[4 * g] = d.x; r[4 * g + 1] = d.y; r[4 * g + 2] = d.z; r[4 * g + 3] = d.w;
     }
   }
   static __device__ __forceinline__ void load(const char* gbase, int Vh, int par, int mu, int cb, Cplx<R> U[3][3]) {
-    const float4* p = reinterpret_cast<const float4*>(gbase) + (size_t)((par * 4 + mu) * 3) * Vh + cb;
+    const float4* p = reinterpret_cast<const float4*>(gbase) + link_index(par, mu, 0, cb, Vh, 3);
     float r[12];
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
-      const v4f d = ldg<v4f>(p + (size_t)g * Vh);
+      const v4f d = ldg<v4f>(p + (size_t)g * kSiteTile);
       r[4 * g] = d.x; r[4 * g + 1] = d.y; r[4 * g + 2] = d.z; r[4 * g + 3] = d.w;
     }
 #pragma unroll
@@ -401,20 +425,20 @@ template <> struct LinkIO<F32> {
 template <int P> struct LinkIO16 {
   using R = float;
   static __device__ __forceinline__ void load_raw(const char* gbase, int Vh, int par, int mu, int cb, R r[12]) {
-    const uint2* p = reinterpret_cast<const uint2*>(gbase) + (size_t)((par * 4 + mu) * 3) * Vh + cb;
+    const uint2* p = reinterpret_cast<const uint2*>(gbase) + link_index(par, mu, 0, cb, Vh, 3);
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
-      const v2u d = ldg<v2u>(p + (size_t)g * Vh);
+      const v2u d = ldg<v2u>(p + (size_t)g * kSiteTile);
       unpack2<P>(d.x, r[4 * g], r[4 * g + 1]);
       unpack2<P>(d.y, r[4 * g + 2], r[4 * g + 3]);
     }
   }
   static __device__ __forceinline__ void load(const char* gbase, int Vh, int par, int mu, int cb, Cplx<R> U[3][3]) {
-    const uint2* p = reinterpret_cast<const uint2*>(gbase) + (size_t)((par * 4 + mu) * 3) * Vh + cb;
+    const uint2* p = reinterpret_cast<const uint2*>(gbase) + link_index(par, mu, 0, cb, Vh, 3);
     float r[12];
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
-      const v2u d = ldg<v2u>(p + (size_t)g * Vh);
+      const v2u d = ldg<v2u>(p + (size_t)g * kSiteTile);
       unpack2<P>(d.x, r[4 * g], r[4 * g + 1]);
       unpack2<P>(d.y, r[4 * g + 2], r[4 * g + 3]);
     }

@@ -119,20 +119,36 @@ __device__ __forceinline__ void accumulate_scaled(Cplx<float> acc[4][3], const C
   }
 }
 
-// w = U h (fwd) or U^dag h (bwd), two colour vectors
+// w = U h (fwd) or U^dag h (bwd), two colour vectors.  Each row is one
+// multiply-add chain per real and imaginary part (4 FMAs per complex product
+// after the first), not products rounded and then added.
 template <bool ADJ, class R>
 __device__ __forceinline__ void colour_mul(const Cplx<R> U[3][3], const Cplx<R> h[2][3], Cplx<R> w[2][3]) {
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      Cplx<R> s = {0, 0};
+      R re = 0, im = 0;
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        const Cplx<R> t = ADJ ? cjmul(U[b][a], h[k][b]) : cmul(U[a][b], h[k][b]);
-        s = add(s, t);
+        const Cplx<R> u = ADJ ? U[b][a] : U[a][b];
+        const Cplx<R> x = h[k][b];
+        if (b == 0) {
+          re = u.re * x.re;
+          im = u.re * x.im;
+        } else {
+          re = u.re * x.re + re;
+          im = u.re * x.im + im;
+        }
+        if constexpr (ADJ) {  // conj(u) x
+          re = u.im * x.im + re;
+          im = im - u.im * x.re;
+        } else {
+          re = re - u.im * x.im;
+          im = u.im * x.re + im;
+        }
       }
-      w[k][a] = s;
+      w[k][a] = {re, im};
     }
   }
 }
@@ -423,10 +439,25 @@ __device__ __forceinline__ void hop_dir_single(const DslashArgs& A, const FieldD
       if (fb == 0) LinkIO<P>::load(A.gauge, g.Vh, A.out_par, MU, cb, U);
       else LinkIO<P>::load(A.gauge, g.Vh, 1 - A.out_par, MU, nb, U);
     }
-    if constexpr (PRO) load_bidiag<P>(in, f, nb, s, g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v);
-    else SpinorIO<P>::load(in, f, nb, s, v);
+    // int16 storage: the stored integers enter the projection and the colour
+    // product unscaled; the site's scale (and 1/32767) joins in the
+    // accumulation, one multiply-add per result instead of one multiply per
+    // loaded value
+    constexpr bool kI16Raw = P == I16 && STAGE && !PRO;
+    float sc16 = 1.f;
+    if constexpr (kI16Raw) {
+      uint32_t q[12];
+      SpinorIO<P>::load_packed(in, f, nb, s, q, sc16);
+      sc16 *= 1.0f / 32767.0f;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = {v[2 * k], v[2 * k + 1]};
+      for (int k = 0; k < 12; ++k)
+        psi[k / 3][k % 3] = {(R)(int16_t)(uint16_t)(q[k] & 0xffffu), (R)(int16_t)(uint16_t)(q[k] >> 16)};
+    } else {
+      if constexpr (PRO) load_bidiag<P>(in, f, nb, s, g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v);
+      else SpinorIO<P>::load(in, f, nb, s, v);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = {v[2 * k], v[2 * k + 1]};
+    }
     if (fb == 0) project<MU, SF>(psi, h);
     else project<MU, SB>(psi, h);
     if (flip) {
@@ -435,12 +466,14 @@ __device__ __forceinline__ void hop_dir_single(const DslashArgs& A, const FieldD
 #pragma unroll
         for (int a = 0; a < 3; ++a) h[k][a] = {-h[k][a].re, -h[k][a].im};
     }
-    if (fb == 0) {
-      colour_mul<false>(U, h, w);
-      accumulate<MU, SF>(acc, w);
+    if (fb == 0) colour_mul<false>(U, h, w);
+    else colour_mul<true>(U, h, w);
+    if constexpr (kI16Raw) {
+      if (fb == 0) accumulate_scaled<MU, SF>(acc, w, sc16);
+      else accumulate_scaled<MU, SB>(acc, w, sc16);
     } else {
-      colour_mul<true>(U, h, w);
-      accumulate<MU, SB>(acc, w);
+      if (fb == 0) accumulate<MU, SF>(acc, w);
+      else accumulate<MU, SB>(acc, w);
     }
     pin_acc(acc);
   }
@@ -721,8 +754,17 @@ __device__ __forceinline__ int block_first_site(const DslashArgs& A, int q, int 
 // arithmetic variants fit 128 (4 waves per SIMD).
 template <int P> constexpr int kMaxThreads = P == F64 ? 512 : 1024;
 
+#ifndef MDWF_WAVES_PER_EU
+#define MDWF_WAVES_PER_EU 0
+#endif
+#if MDWF_WAVES_PER_EU > 0
+#define MDWF_OCC __attribute__((amdgpu_waves_per_eu(MDWF_WAVES_PER_EU)))
+#else
+#define MDWF_OCC
+#endif
+
 template <int P, bool HOP, bool DAG, bool PRO, bool STAGE, bool CGU>
-__global__ __launch_bounds__(kMaxThreads<P>) void dslash5_kernel(DslashArgs A) {
+__global__ __launch_bounds__(kMaxThreads<P>) MDWF_OCC void dslash5_kernel(DslashArgs A) {
   using R = typename PrecTraits<P>::Real;
   extern __shared__ __align__(16) unsigned char smem[];
   const int CB = 1 << A.cb_log2;

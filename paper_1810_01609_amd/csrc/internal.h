@@ -21,6 +21,7 @@ struct DevBuf {
 
 struct ProfRec {
   int cls;
+  int stratum;  // 0 outside the CG iteration loop (always timed), 1 inside (sampled)
   double bytes;
   hipEvent_t e0, e1;
 };
@@ -42,14 +43,17 @@ struct mdwf_ctx {
   std::string err;
   // profiling
   int prof = 0;            // 0 off, 1 every launch, N > 1 one CG iteration in N
+  bool prof_loop = false;  // inside the CG iteration loop (sampled stratum)
   bool prof_skip = false;  // inside a CG iteration that is not sampled
   int64_t prof_iter = 0;   // CG iterations seen while sampling
   std::vector<mdwf::ProfRec> pending;
   std::vector<hipEvent_t> events;
-  int64_t prof_launches[MDWF_PROF_NCLASS] = {};
-  int64_t prof_timed[MDWF_PROF_NCLASS] = {};
-  double prof_ms[MDWF_PROF_NCLASS] = {};
-  double prof_bytes[MDWF_PROF_NCLASS] = {};
+  // per class and stratum (0 outside the CG loop, 1 inside): launches,
+  // timed launches, timed ms, modelled bytes
+  int64_t prof_launches[MDWF_PROF_NCLASS][2] = {};
+  int64_t prof_timed[MDWF_PROF_NCLASS][2] = {};
+  double prof_ms[MDWF_PROF_NCLASS][2] = {};
+  double prof_bytes[MDWF_PROF_NCLASS][2] = {};
   // autotuner: key -> log2 of sites per workgroup
   int tune_mode = 0;
   std::map<std::string, int> tune;

@@ -103,8 +103,6 @@ struct BlasArgs {
 };
 constexpr int kBlasThreads = 256;
 
-// CG: x += alpha p, r -= alpha q, partials of |r|^2.   a=x(px) b=p c=r d=q (ps)
-hipError_t blas_cg_xr(BlasArgs A, int px, int ps, hipStream_t st);
 // CG: p = r + beta p and pt = M_phi p.   a=p b=r c=pt, coef
 hipError_t blas_cg_p(BlasArgs A, int ps, hipStream_t st);
 // out = ca * in + cb * out  (cb == 0: out is not read).  a=in(pin) b=out(pout);

@@ -61,22 +61,22 @@ __global__ __launch_bounds__(256) void k_gauge(Geom g, const double* user, char*
   const int i4 = lex_index(g, par, cb);
   const double* u = user + ((size_t)i4 * 4 + mu) * 18;  // rows 0,1 = 12 doubles
   if constexpr (P == F64) {
-    double2* o = reinterpret_cast<double2*>(out) + (size_t)((par * 4 + mu) * 6) * g.Vh + cb;
+    double2* o = reinterpret_cast<double2*>(out) + link_index(par, mu, 0, cb, g.Vh, 6);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) o[(size_t)k * g.Vh] = make_double2(u[2 * k], u[2 * k + 1]);
+    for (int k = 0; k < 6; ++k) o[(size_t)k * kSiteTile] = make_double2(u[2 * k], u[2 * k + 1]);
   } else if constexpr (P == F32) {
-    float4* o = reinterpret_cast<float4*>(out) + (size_t)((par * 4 + mu) * 3) * g.Vh + cb;
+    float4* o = reinterpret_cast<float4*>(out) + link_index(par, mu, 0, cb, g.Vh, 3);
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      o[(size_t)k * g.Vh] = make_float4((float)u[4 * k], (float)u[4 * k + 1], (float)u[4 * k + 2], (float)u[4 * k + 3]);
+      o[(size_t)k * kSiteTile] = make_float4((float)u[4 * k], (float)u[4 * k + 1], (float)u[4 * k + 2], (float)u[4 * k + 3]);
   } else {
-    uint2* o = reinterpret_cast<uint2*>(out) + (size_t)((par * 4 + mu) * 3) * g.Vh + cb;
+    uint2* o = reinterpret_cast<uint2*>(out) + link_index(par, mu, 0, cb, g.Vh, 3);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       uint2 q;
       q.x = pack2<P>((float)u[4 * k], (float)u[4 * k + 1]);
       q.y = pack2<P>((float)u[4 * k + 2], (float)u[4 * k + 3]);
-      o[(size_t)k * g.Vh] = q;
+      o[(size_t)k * kSiteTile] = q;
     }
   }
 }

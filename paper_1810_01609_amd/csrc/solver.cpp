@@ -533,6 +533,7 @@ extern "C" mdwf_status mdwf_job_step(mdwf_ctx* c, mdwf_job* const* jobs, int32_t
     const int chunk = std::min(remaining, slots[0].job->opts.check_every);
     const int* act = &S_d[0].active;
     for (int it = 0; it < chunk && e == hipSuccess; ++it) {
+      c->prof_loop = true;
       c->prof_skip = c->prof > 1 && (c->prof_iter++ % c->prof) != 0;
       e = run_prog(c, j0->g, geom, ps, prog_A1_pt(), PT, nullptr, T, coef_d, n, act, stride, nullptr, 0,
                    MDWF_PROF_DSLASH_INNER, true);
@@ -573,6 +574,7 @@ extern "C" mdwf_status mdwf_job_step(mdwf_ctx* c, mdwf_job* const* jobs, int32_t
       }
     }
     c->prof_skip = false;
+    c->prof_loop = false;
     if (e != hipSuccess) return hip_err(c, e, "CG iteration");
     remaining -= chunk;
     // poll the device state
