@@ -34,10 +34,14 @@ __host__ __device__ __forceinline__ size_t round_up(size_t v, size_t a) { return
 
 // Spinor fields are stored in tiles of kSiteTile consecutive sites: a tile
 // holds all L5 slices and all 16-byte groups of its sites, site fastest
-// ([tile][s][group][site in tile]), so a workgroup's slice columns and the
-// x/y neighbours of its sites sit in a few contiguous pages instead of one
-// page per (slice, group) stream.
-constexpr int kSiteTile = 64;
+// ([tile][s][group][site in tile]).  With 16-site tiles (the stencil's
+// workgroup width) the loads of one wavefront (16 sites x 4 slices) cover one
+// contiguous block of memory, and a workgroup's whole 5D column is one
+// contiguous block, instead of one short run per (slice, group) stream.
+#ifndef MDWF_SITE_TILE
+#define MDWF_SITE_TILE 16
+#endif
+constexpr int kSiteTile = MDWF_SITE_TILE;  // a power of two
 __host__ __device__ __forceinline__ size_t padded_vh(int Vh) { return round_up((size_t)Vh, kSiteTile); }
 // index, in 16-byte units, of group g of slice s of site cb (G groups per site)
 __host__ __device__ __forceinline__ size_t tile_index(int cb, int s, int g, int L5, int G) {
