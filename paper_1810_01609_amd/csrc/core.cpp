@@ -210,14 +210,43 @@ void prof_begin(mdwf_ctx* c, hipEvent_t* e0) {
   t.launches = 0;
 }
 
+// fold the finished records whose chunk has been committed (all records when
+// the loop is not running); returns their events to the pool
+static void fold_records(mdwf_ctx* c) {
+  std::vector<ProfRec> keep;
+  for (auto& r : c->pending) {
+    if (r.pos >= 0 && r.chunk > c->prof_committed) {
+      keep.push_back(r);
+      continue;
+    }
+    if (!r.idle) {
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, r.e0, r.e1);
+      const int sr = r.pos >= 0 ? 1 : 0;
+      if (sr == 0) {  // launches and bytes of the loop stratum come from the chunk commit
+        c->prof_launches[r.cls][0] += 1;
+        c->prof_bytes[r.cls][0] += r.bytes;
+      }
+      c->prof_timed[r.cls][sr] += 1;
+      c->prof_ms[r.cls][sr] += ms;
+    }
+    c->events.push_back(r.e0);
+    c->events.push_back(r.e1);
+  }
+  c->pending.swap(keep);
+}
+
 void prof_end(mdwf_ctx* c, int cls, double bytes, hipEvent_t e0) {
   if (!c->prof) return;
-  const int sr = c->prof_loop ? 1 : 0;
-  if (e0 == nullptr) {  // an iteration that is not sampled: counted, not timed
-    c->prof_launches[cls][sr] += 1;
-    c->prof_bytes[cls][sr] += bytes;
-    return;
+  const int pos = c->prof_pos;
+  if (pos >= 0) {  // inside the CG loop: counted per position until the poll
+    const size_t k = (size_t)pos * MDWF_PROF_NCLASS + cls;
+    if (k < c->prof_chunk_n.size()) {
+      c->prof_chunk_n[k] += 1;
+      c->prof_chunk_b[k] += bytes;
+    }
   }
+  if (e0 == nullptr) return;  // an iteration that is not sampled: counted, not timed
   LaunchTiming& t = launch_timing();
   hipEvent_t e1 = t.stop;
   const int n = t.launches;
@@ -227,22 +256,39 @@ void prof_end(mdwf_ctx* c, int cls, double bytes, hipEvent_t e0) {
     c->events.push_back(e1);
     return;
   }
-  c->pending.push_back(ProfRec{cls, sr, bytes, e0, e1});
-  if (c->pending.size() > 4096) {
-    // fold finished records so the pool stays bounded
+  c->pending.push_back(ProfRec{cls, pos, c->prof_chunk, false, bytes, e0, e1});
+  if (c->pending.size() > 8192) {
+    // keep the event pool bounded
     (void)hipEventSynchronize(e1);
-    for (auto& r : c->pending) {
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, r.e0, r.e1);
-      c->prof_launches[r.cls][r.stratum] += 1;
-      c->prof_timed[r.cls][r.stratum] += 1;
-      c->prof_ms[r.cls][r.stratum] += ms;
-      c->prof_bytes[r.cls][r.stratum] += r.bytes;
-      c->events.push_back(r.e0);
-      c->events.push_back(r.e1);
-    }
-    c->pending.clear();
+    fold_records(c);
   }
+}
+
+void prof_chunk_begin(mdwf_ctx* c, int chunk) {
+  if (!c->prof) return;
+  c->prof_chunk += 1;
+  c->prof_chunk_n.assign((size_t)chunk * MDWF_PROF_NCLASS, 0.0);
+  c->prof_chunk_b.assign((size_t)chunk * MDWF_PROF_NCLASS, 0.0);
+}
+
+void prof_chunk_commit(mdwf_ctx* c, const std::vector<double>& active_frac) {
+  if (!c->prof) return;
+  const int npos = (int)(c->prof_chunk_n.size() / MDWF_PROF_NCLASS);
+  for (int pos = 0; pos < npos && pos < (int)active_frac.size(); ++pos) {
+    const double f = active_frac[pos];
+    if (f <= 0.0) continue;
+    for (int cls = 0; cls < MDWF_PROF_NCLASS; ++cls) {
+      const size_t k = (size_t)pos * MDWF_PROF_NCLASS + cls;
+      c->prof_launches[cls][1] += (int64_t)c->prof_chunk_n[k];
+      c->prof_bytes[cls][1] += c->prof_chunk_b[k] * f;
+    }
+  }
+  for (auto& r : c->pending)
+    if (r.pos >= 0 && r.chunk == c->prof_chunk && (r.pos >= (int)active_frac.size() || active_frac[r.pos] <= 0.0))
+      r.idle = true;
+  c->prof_committed = c->prof_chunk;
+  c->prof_chunk_n.clear();
+  c->prof_chunk_b.clear();
 }
 
 // ---------------------------------------------------------------------------
@@ -607,29 +653,26 @@ mdwf_status mdwf_profile_enable(mdwf_ctx* c, int32_t on) {
   if (on < 0) return set_err(c, MDWF_EINVAL, "mdwf_profile_enable: negative mode");
   c->prof = on;
   c->prof_skip = false;
-  c->prof_loop = false;
+  c->prof_pos = -1;
   c->prof_iter = 0;
   return MDWF_OK;
 }
 
 static void fold_profile(mdwf_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
-  for (auto& r : c->pending) {
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, r.e0, r.e1);
-    c->prof_launches[r.cls][r.stratum] += 1;
-    c->prof_timed[r.cls][r.stratum] += 1;
-    c->prof_ms[r.cls][r.stratum] += ms;
-    c->prof_bytes[r.cls][r.stratum] += r.bytes;
-    c->events.push_back(r.e0);
-    c->events.push_back(r.e1);
-  }
-  c->pending.clear();
+  fold_records(c);
 }
 
 mdwf_status mdwf_profile_reset(mdwf_ctx* c) {
   if (c == nullptr) return MDWF_EINVAL;
   fold_profile(c);
+  // records of a chunk that never reached its poll (an error path) are dropped
+  for (auto& r : c->pending) {
+    c->events.push_back(r.e0);
+    c->events.push_back(r.e1);
+  }
+  c->pending.clear();
+  c->prof_committed = c->prof_chunk;
   for (int k = 0; k < MDWF_PROF_NCLASS; ++k)
     for (int sr = 0; sr < 2; ++sr) {
       c->prof_launches[k][sr] = 0;

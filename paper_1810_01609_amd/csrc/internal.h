@@ -21,7 +21,9 @@ struct DevBuf {
 
 struct ProfRec {
   int cls;
-  int stratum;  // 0 outside the CG iteration loop (always timed), 1 inside (sampled)
+  int pos;        // iteration position within its CG chunk, -1 outside the loop
+  int64_t chunk;  // CG chunk the launch belongs to (pos >= 0)
+  bool idle;      // every slot was frozen at that iteration (set at the poll)
   double bytes;
   hipEvent_t e0, e1;
 };
@@ -43,9 +45,16 @@ struct mdwf_ctx {
   std::string err;
   // profiling
   int prof = 0;            // 0 off, 1 every launch, N > 1 one CG iteration in N
-  bool prof_loop = false;  // inside the CG iteration loop (sampled stratum)
   bool prof_skip = false;  // inside a CG iteration that is not sampled
   int64_t prof_iter = 0;   // CG iterations seen while sampling
+  // CG loop accounting: launches and bytes of the current chunk per iteration
+  // position, committed at the poll with the fraction of slots that were
+  // still iterating (launches where every slot was frozen do no work and are
+  // left out of both the time and the byte totals)
+  int prof_pos = -1;          // position in the current chunk, -1 outside the loop
+  int64_t prof_chunk = 0;     // current chunk id
+  int64_t prof_committed = 0; // chunks whose positions are known
+  std::vector<double> prof_chunk_n, prof_chunk_b;  // [pos * NCLASS + cls]
   std::vector<mdwf::ProfRec> pending;
   std::vector<hipEvent_t> events;
   // per class and stratum (0 outside the CG loop, 1 inside): launches,
@@ -140,5 +149,10 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* g, const Geom& geom, int prec
                     const CgFuse* fuse = nullptr);
 void prof_begin(mdwf_ctx* c, hipEvent_t* e0);
 void prof_end(mdwf_ctx* c, int cls, double bytes, hipEvent_t e0);
+// CG loop accounting (see mdwf_ctx): a chunk of `chunk` iterations starts;
+// after the poll, active_frac[pos] is the fraction of slots that iterated at
+// position pos
+void prof_chunk_begin(mdwf_ctx* c, int chunk);
+void prof_chunk_commit(mdwf_ctx* c, const std::vector<double>& active_frac);
 
 }  // namespace mdwf

@@ -532,8 +532,11 @@ extern "C" mdwf_status mdwf_job_step(mdwf_ctx* c, mdwf_job* const* jobs, int32_t
     const int n = (int)slots.size();
     const int chunk = std::min(remaining, slots[0].job->opts.check_every);
     const int* act = &S_d[0].active;
+    std::vector<int> it0(n);
+    for (int i = 0; i < n; ++i) it0[i] = slots[i].job->st[slots[i].r].iters;
+    prof_chunk_begin(c, chunk);
     for (int it = 0; it < chunk && e == hipSuccess; ++it) {
-      c->prof_loop = true;
+      c->prof_pos = it;
       c->prof_skip = c->prof > 1 && (c->prof_iter++ % c->prof) != 0;
       e = run_prog(c, j0->g, geom, ps, prog_A1_pt(), PT, nullptr, T, coef_d, n, act, stride, nullptr, 0,
                    MDWF_PROF_DSLASH_INNER, true);
@@ -574,7 +577,7 @@ extern "C" mdwf_status mdwf_job_step(mdwf_ctx* c, mdwf_job* const* jobs, int32_t
       }
     }
     c->prof_skip = false;
-    c->prof_loop = false;
+    c->prof_pos = -1;
     if (e != hipSuccess) return hip_err(c, e, "CG iteration");
     remaining -= chunk;
     // poll the device state
@@ -582,6 +585,14 @@ extern "C" mdwf_status mdwf_job_step(mdwf_ctx* c, mdwf_job* const* jobs, int32_t
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_err(c, e, "state poll");
     for (int i = 0; i < n; ++i) slots[i].job->st[slots[i].r] = c->st_host[i];
+    if (c->prof) {  // which iterations of the chunk did work, for the kernel-time accounting
+      std::vector<double> frac(chunk, 0.0);
+      for (int i = 0; i < n; ++i) {
+        const int done = std::min(chunk, std::max(0, c->st_host[i].iters - it0[i]));
+        for (int pos = 0; pos < done; ++pos) frac[pos] += 1.0 / n;
+      }
+      prof_chunk_commit(c, frac);
+    }
     bool changed = false;
     for (int i = 0; i < n && st == MDWF_OK; ++i) {
       mdwf_job* j = slots[i].job;
