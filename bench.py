@@ -215,6 +215,10 @@ def main():
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--tune", action="store_true", help="enable the launch autotuner")
     ap.add_argument("--tune-save", default=None, help="dslash-only: write the tuned launch table here")
+    ap.add_argument("--delta", type=float, default=None,
+                    help="reliable-update threshold: an update when |r| falls below delta x its maximum since the "
+                         "last (default by inner precision: 0.01 for f32, 0.1 for 16-bit)")
+    ap.add_argument("--check-every", type=int, default=8, help="CG iterations between host polls of the solver state")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time the solves without per-launch HIP events (no roofline figures)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -259,7 +263,7 @@ def main():
     del U
     eta = torch.zeros((nrhs,) + act.spinor_shape(), dtype=torch.complex128, device="cuda")
     psi = torch.zeros_like(eta)
-    opts = M.CGOpts.make(tol=1e-10, inner=args.inner, delta=0.1)
+    opts = M.CGOpts.make(tol=1e-10, inner=args.inner, delta=args.delta, check_every=args.check_every)
     opts64 = M.CGOpts.make(tol=1e-10, inner="f64")
 
     def sources(n):
@@ -336,7 +340,7 @@ def main():
                          f"c5={cfg['c5']} M5={cfg['M5']} mq={cfg['mq']}, links exp(i{cfg['eps']}H) "
                          f"seed {cfg['seed']}, {cfg['source']} source, even-odd CGNR to 1e-10, "
                          f"{args.inner} inner + f64 reliable updates"),
-            "lattice": list(L), "L5": L5, "nrhs": nrhs, "inner": args.inner, "tol": 1e-10,
+            "lattice": list(L), "L5": L5, "nrhs": nrhs, "inner": args.inner, "tol": 1e-10, "delta": opts.delta,
         },
         "roofline": {
             "bound": "hbm",

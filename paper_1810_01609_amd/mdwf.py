@@ -65,11 +65,18 @@ class CGOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("delta", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("inner", ctypes.c_int32), ("use_initial_guess", ctypes.c_int32), ("check_every", ctypes.c_int32)]
 
+    # reliable-update threshold by inner precision: an FP32 iteration keeps
+    # ~7 digits, so its residual may fall 100x between FP64 updates; 16-bit
+    # storage (~3 digits) updates every 10x
+    DEFAULT_DELTA = {F64: 0.1, F32: 0.01, F16: 0.1, BF16: 0.1, I16: 0.1}
+
     @classmethod
-    def make(cls, tol=1e-10, inner=F64, delta=0.1, max_iter=100000, use_initial_guess=0, check_every=0):
+    def make(cls, tol=1e-10, inner=F64, delta=None, max_iter=100000, use_initial_guess=0, check_every=0):
         o = cls()
-        o.tol, o.delta, o.max_iter = float(tol), float(delta), int(max_iter)
         o.inner = PREC[inner] if isinstance(inner, str) else int(inner)
+        if delta is None:
+            delta = cls.DEFAULT_DELTA.get(o.inner, 0.1)
+        o.tol, o.delta, o.max_iter = float(tol), float(delta), int(max_iter)
         o.use_initial_guess, o.check_every = int(use_initial_guess), int(check_every)
         return o
 
