@@ -72,11 +72,14 @@ def cpu_baseline(cfg, gpu_iters_f64: int):
     U = S.gauge_field(cfg["L"], cfg["eps"], cfg["seed"])
     x = S.random_spinor(cfg["L"], cfg["L5"], 7)
     t = {}
-    for name, fn in (("hop", lambda: O.hop(U, x, act)), ("m5_inv", lambda: O.m5_inv(x, act)),
-                     ("m_phi", lambda: O.m_phi(x, act))):
-        t0 = time.perf_counter()
-        fn()
-        t[name] = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+
+    with threadpool_limits(limits=1):  # one thread, whatever BLAS NumPy links
+        for name, fn in (("hop", lambda: O.hop(U, x, act)), ("m5_inv", lambda: O.m5_inv(x, act)),
+                         ("m_phi", lambda: O.m_phi(x, act))):
+            t0 = time.perf_counter()
+            fn()
+            t[name] = time.perf_counter() - t0
     per_iter = 4 * t["hop"] + 4 * t["m5_inv"] + 4 * t["m_phi"]
     setup = 3 * t["hop"] + 4 * t["m5_inv"] + 3 * t["m_phi"]
     t_solve = setup + per_iter * gpu_iters_f64
@@ -92,7 +95,25 @@ def cpu_baseline(cfg, gpu_iters_f64: int):
         "component_seconds": t,
         "seconds_per_iteration": per_iter,
         "host_cpus": os.cpu_count(),
+        "cpu_model": _cpu_model(),
     }
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def stats_flops(stats, nrhs):
+    """Modelled flops of the timed solves (the library's per-iteration count
+    times the iterations of each RHS)."""
+    return sum(s["flops"] for s in stats)
 
 
 def serve_bench(args):
@@ -354,7 +375,9 @@ def main():
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "launches": d["launches"],
             "traffic_note": traffic_note,
+            "cache_resident": bool(cfg["L"][0] * cfg["L"][1] * cfg["L"][2] * cfg["L"][3] * L5 * 48 < 256e6),
         },
+        "tflops": (stats_flops(stats, nrhs) / elapsed / 1e12) if ok else None,
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
         "solve": {
             "iters": max(s["iters"] for s in stats[-nrhs:]),

@@ -68,8 +68,9 @@ void iter_model(const Geom& g, int ps, double& bytes, double& flops) {
   // A1 2, A2 3, B1 2, B2 with the fused update 5 spinor transfers + x read/write,
   // 4 link sweeps; p = r + beta p with M_phi p 4 transfers
   bytes = ne * sb * 12 + 2 * ne * sx + 4 * links + ne * 4 * sb;
-  // hop 1320/site x4, M_phi 72 x3, M5^-1 96 x4, M5 72, xpay 48 x2, CG BLAS 192
-  flops = ne * (4 * 1320.0 + 3 * 72 + 4 * 96 + 72 + 2 * 48 + 192);
+  // hop 1320/site x4, M_phi 72 x4 (A1, B1, B2, p-update), M5^-1 96 x4, M5 72,
+  // xpay 48 x2, CG BLAS 192
+  flops = ne * (4 * 1320.0 + 4 * 72 + 4 * 96 + 72 + 2 * 48 + 192);
 }
 
 // one fused slot of a step
