@@ -116,6 +116,61 @@ def stats_flops(stats, nrhs):
     return sum(s["flops"] for s in stats)
 
 
+def fh_bench(args):
+    """Feynman-Hellmann sequential propagators: per step, the Z2 source, the
+    propagator solve, the 4D read-out, the current source (axial g_x g_y g_t,
+    mask 11) and the sequential solve, all on the device."""
+    import torch
+
+    import mdwf_synth as S
+    from paper_1810_01609_amd import mdwf as M
+
+    cfg = S.CONFIGS[args.workload]
+    inner = args.inner or ("f16" if args.workload in ("c3", "c4") else "f32")
+    L, L5 = cfg["L"], cfg["L5"]
+    act = M.Action.make(L, L5, cfg["b5"], cfg["c5"], cfg["M5"], cfg["mq"])
+    U = S.gauge_field(L, cfg["eps"], cfg["seed"])
+    ctx = M.Context(0)
+    g = ctx.gauge_load(L, U, precs=("f64", inner))
+    del U
+    eta = torch.zeros(act.spinor_shape(), dtype=torch.complex128, device="cuda")
+    psi = torch.zeros_like(eta)
+    q = torch.zeros(act.spinor_shape()[1:], dtype=torch.complex128, device="cuda")
+    eta2 = torch.zeros_like(eta)
+    fh = torch.zeros_like(eta)
+    opts = M.CGOpts.make(tol=1e-10, inner=inner)
+
+    def step():
+        seed = cfg["z2_seed"] if cfg["source"] == "z2" else 1
+        ctx.source_z2(act, seed, 0, eta)
+        s1 = ctx.solve(g, act, opts, eta, psi)[0]
+        ctx.propagator_4d(act, psi, q)
+        ctx.current_source(act, 11, q, eta2)
+        s2 = ctx.solve(g, act, opts, eta2, fh)[0]
+        return s1, s2
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ok = all(a["converged"] == 1 and b["converged"] == 1 for a, b in stats)
+    g.free()
+    ctx.close()
+    line = {
+        "metric": "Feynman-Hellmann propagator pairs/s (propagator + sequential solve, each to rel-res 1e-10)",
+        "value": args.steps / el if ok else 0.0, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if inner == "f64" else "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload} Feynman-Hellmann: Z2 source, axial current g_x g_y g_t, {inner} inner"},
+        "iters": [stats[-1][0]["iters"], stats[-1][1]["iters"]],
+        "rel_res_full": [stats[-1][0]["rel_res_full"], stats[-1][1]["rel_res_full"]],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def serve_bench(args):
     """c5: a Poisson stream of solves served with continuous batching."""
     import mdwf_synth as S
@@ -240,6 +295,7 @@ def main():
                     help="reliable-update threshold: an update when |r| falls below delta x its maximum since the "
                          "last (default by inner precision: 0.01 for f32, 0.1 for 16-bit)")
     ap.add_argument("--check-every", type=int, default=8, help="CG iterations between host polls of the solver state")
+    ap.add_argument("--fh", action="store_true", help="Feynman-Hellmann propagator pairs instead of single solves")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time the solves without per-launch HIP events (no roofline figures)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -264,6 +320,9 @@ def main():
 
     if args.workload == "c5":
         serve_bench(args)
+        return
+    if args.fh:
+        fh_bench(args)
         return
     if args.dslash_only:
         dslash_bench(args)

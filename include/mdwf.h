@@ -193,6 +193,30 @@ MDWF_API mdwf_status mdwf_source_point(mdwf_ctx *ctx, const mdwf_action *act, co
 MDWF_API mdwf_status mdwf_source_z2(mdwf_ctx *ctx, const mdwf_action *act, uint64_t seed, int32_t rhs_index,
                            void *eta);
 
+/* ---- Feynman-Hellmann sequential propagator ------------------------------- */
+/* The paper's propagator with a current inserted at every time slice
+ * ("Current State of the Art", Physics algorithms related): from a solved
+ * 5D propagator psi, the 4D quark field q is read off the walls, a current
+ * Gamma is applied at every site, the result is wall-injected as a new 5D
+ * source, and mdwf_solve gives the sequential propagator. */
+
+/* q (device, complex128 [rhs][t][z][y][x][spin][colour], caller-allocated,
+ * nrhs 4D fields back to back) = P- psi_0 + P+ psi_{L5-1} for each of the
+ * nrhs 5D fields in psi (device, user layout, back to back).  Asynchronous on
+ * the context stream.  EINVAL on a bad action, nrhs < 1 or NULL pointers. */
+MDWF_API mdwf_status mdwf_propagator_4d(mdwf_ctx *ctx, const mdwf_action *act, int32_t nrhs, const void *psi,
+                                       void *q);
+
+/* eta (device, user layout, nrhs 5D fields, caller-allocated; every entry is
+ * written) = wall injection of Gamma q: eta_0 = P- Gamma q,
+ * eta_{L5-1} = P+ Gamma q, zero on the other slices.  Gamma =
+ * g_x^b0 g_y^b1 g_z^b2 g_t^b3 with gamma_mask = b0 + 2 b1 + 4 b2 + 8 b3
+ * (0: identity, 15: gamma5; the axial current g_z g5 is mask 11 up to sign).
+ * Asynchronous.  EINVAL on a bad action, mask outside [0, 15], nrhs < 1 or
+ * NULL pointers; q and eta must not overlap. */
+MDWF_API mdwf_status mdwf_current_source(mdwf_ctx *ctx, const mdwf_action *act, int32_t nrhs, int32_t gamma_mask,
+                                        const void *q, void *eta);
+
 /* ---- operator application ------------------------------------------------- */
 
 /* out = op(in) for nrhs fields (device, user layout).  The operator is

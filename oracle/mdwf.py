@@ -40,6 +40,7 @@ __all__ = [
     "point_source", "splitmix64", "z2_noise", "z2_source", "wall_inject",
     "gauge_transform_links", "gauge_transform_spinor",
     "dirac_at_sites", "vdot", "norm2",
+    "gamma_product", "propagator_4d", "current_source", "fh_solve", "fh_operator",
 ]
 
 # ---------------------------------------------------------------------------
@@ -570,3 +571,47 @@ def dirac_at_sites(U, psi, act, sites):
             h += (IDENT4 - GAMMA[mu]) @ tf + (IDENT4 + GAMMA[mu]) @ tb
         out.append(local - 0.5 * h)
     return np.array(out)
+
+
+# ---------------------------------------------------------------------------
+# Feynman-Hellmann sequential propagator (paper, "Current State of the Art",
+# Physics algorithms related: one extra propagator carries a current inserted
+# at every time slice, giving all source-sink separations at the cost of one).
+# Readings: the 4D quark field is read off the walls, q = P- psi_0 + P+
+# psi_{L5-1} (the projection that matches the wall injection of a source; no
+# Moebius 4D source factor); the current is a spin matrix Gamma, one of the 16
+# products of gamma matrices, applied at every site; the sequential source is
+# Gamma q, wall-injected like any 4D source; the sequential propagator solves
+# D psi_FH = inject(Gamma q).
+# ---------------------------------------------------------------------------
+def gamma_product(mask: int) -> np.ndarray:
+    """Gamma = g_x^b0 g_y^b1 g_z^b2 g_t^b3 for mask = b0 + 2 b1 + 4 b2 + 8 b3
+    (mask 0 is the identity, mask 15 is gamma5)."""
+    G = IDENT4.copy()
+    for mu in range(4):
+        if (mask >> mu) & 1:
+            G = G @ GAMMA[mu]
+    return G
+
+
+def propagator_4d(psi, act):
+    """4D field q[t][z][y][x][spin][col] = P- psi_0 + P+ psi_{L5-1}."""
+    return _spin(PMINUS, psi[0]) + _spin(PPLUS, psi[act.L5 - 1])
+
+
+def current_source(q, act, mask):
+    """Sequential 5D source: the current Gamma applied to q at every site,
+    wall-injected."""
+    return wall_inject(_spin(gamma_product(mask), q), act)
+
+
+def fh_solve(U, psi, act, mask, tol=1e-12):
+    """psi_FH = D^{-1} inject(Gamma q(psi))."""
+    return solve(U, current_source(propagator_4d(psi, act), act, mask), act, tol=tol)
+
+
+def fh_operator(psi, act, mask):
+    """J psi = inject(Gamma q(psi)): the 5D operator of the current
+    insertion, so that D(lambda) = D + lambda J is the action with the
+    current added; d/dlambda D(lambda)^{-1} eta = -D^{-1} J D^{-1} eta."""
+    return current_source(propagator_4d(psi, act), act, mask)

@@ -648,6 +648,40 @@ mdwf_status mdwf_source_z2(mdwf_ctx* c, const mdwf_action* act, uint64_t seed, i
   return hip_err(c, e, "source_z2");
 }
 
+mdwf_status mdwf_propagator_4d(mdwf_ctx* c, const mdwf_action* act, int32_t nrhs, const void* psi, void* q) {
+  if (c == nullptr) return MDWF_EINVAL;
+  std::string msg;
+  if (check_action_msg(act, msg) != MDWF_OK) return set_err(c, MDWF_EINVAL, "mdwf_propagator_4d: %s", msg.c_str());
+  if (psi == nullptr || q == nullptr || nrhs < 1) return set_err(c, MDWF_EINVAL, "mdwf_propagator_4d: bad argument");
+  (void)hipSetDevice(c->device);
+  const Geom g = make_geom(act);
+  hipEvent_t ev;
+  prof_begin(c, &ev);
+  hipError_t e = propagator_4d(g, nrhs, static_cast<const double*>(psi), static_cast<double*>(q), c->stream);
+  prof_end(c, MDWF_PROF_OTHER, (double)nrhs * g.Vh * 2 * 12 * 32, ev);
+  return hip_err(c, e, "propagator_4d");
+}
+
+mdwf_status mdwf_current_source(mdwf_ctx* c, const mdwf_action* act, int32_t nrhs, int32_t gamma_mask, const void* q,
+                                void* eta) {
+  if (c == nullptr) return MDWF_EINVAL;
+  std::string msg;
+  if (check_action_msg(act, msg) != MDWF_OK) return set_err(c, MDWF_EINVAL, "mdwf_current_source: %s", msg.c_str());
+  if (q == nullptr || eta == nullptr || nrhs < 1) return set_err(c, MDWF_EINVAL, "mdwf_current_source: bad argument");
+  if (gamma_mask < 0 || gamma_mask > 15) return set_err(c, MDWF_EINVAL, "mdwf_current_source: gamma_mask in [0, 15]");
+  (void)hipSetDevice(c->device);
+  const Geom g = make_geom(act);
+  const size_t qb = (size_t)nrhs * g.Vh * 2 * 12 * 16, eb = qb * g.L5;
+  const char* qa = static_cast<const char*>(q);
+  const char* ea = static_cast<const char*>(eta);
+  if (qa < ea + eb && ea < qa + qb) return set_err(c, MDWF_EINVAL, "mdwf_current_source: q and eta overlap");
+  hipEvent_t ev;
+  prof_begin(c, &ev);
+  hipError_t e = current_source(g, nrhs, gamma_mask, static_cast<const double*>(q), static_cast<double*>(eta), c->stream);
+  prof_end(c, MDWF_PROF_OTHER, (double)eb + qb, ev);
+  return hip_err(c, e, "current_source");
+}
+
 mdwf_status mdwf_profile_enable(mdwf_ctx* c, int32_t on) {
   if (c == nullptr) return MDWF_EINVAL;
   if (on < 0) return set_err(c, MDWF_EINVAL, "mdwf_profile_enable: negative mode");

@@ -132,5 +132,8 @@ hipError_t layout_gauge(const Geom& g, const double* user, char* out, int p, hip
 hipError_t fill_zero(void* ptr, size_t bytes, hipStream_t st);
 hipError_t source_point(const Geom& g, double* eta, const int x0[4], int spin, int colour, hipStream_t st);
 hipError_t source_z2(const Geom& g, double* eta, uint64_t seed, int rhs_index, hipStream_t st);
+// Feynman-Hellmann sequential source, user layouts, nrhs fields back to back
+hipError_t propagator_4d(const Geom& g, int nrhs, const double* psi, double* q, hipStream_t st);
+hipError_t current_source(const Geom& g, int nrhs, int mask, const double* q, double* eta, hipStream_t st);
 
 }  // namespace mdwf

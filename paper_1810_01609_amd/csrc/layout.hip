@@ -124,6 +124,92 @@ __global__ __launch_bounds__(256) void k_source_z2(Geom g, double* eta, uint64_t
   e[((size_t)s * V4 + i4) * 12 + sc] = make_double2(re, im);
 }
 
+// ---------------------------------------------------------------------------
+// Feynman-Hellmann sequential source (user layouts, FP64).
+// 4D quark field read off the walls: q = P- psi_0 + P+ psi_{L5-1}; in the
+// chiral basis spins 0,1 come from slice L5-1 and spins 2,3 from slice 0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_propagator_4d(Geom g, const double2* psi, double2* q) {
+  const size_t V4 = (size_t)g.Vh * 2;
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;  // i4 * 12 + spin * 3 + colour
+  const size_t r = blockIdx.y;
+  if (idx >= V4 * 12) return;
+  const int spin = (int)(idx % 12) / 3;
+  const int s = spin < 2 ? g.L5 - 1 : 0;
+  q[r * V4 * 12 + idx] = psi[(r * g.L5 + s) * V4 * 12 + idx];
+}
+
+// eta = wall injection of Gamma q: Gamma is a signed permutation in the
+// chiral basis, row a of Gamma q = i^phase[a] q[perm[a]]; eta_0 takes the P-
+// spins (2,3), eta_{L5-1} the P+ spins (0,1), every other slice is zero.
+struct SpinPerm {
+  int perm[4];
+  int phase[4];  // power of i
+};
+
+__global__ __launch_bounds__(256) void k_current_source(Geom g, SpinPerm G, const double2* q, double2* eta) {
+  const size_t V4 = (size_t)g.Vh * 2;
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;  // i4 * 12 + spin * 3 + colour
+  const int s = blockIdx.y;
+  const size_t r = blockIdx.z;
+  if (idx >= V4 * 12) return;
+  const size_t i4 = idx / 12;
+  const int spin = (int)(idx % 12) / 3;
+  const int colour = (int)(idx % 3);
+  const bool wall = (s == 0 && spin >= 2) || (s == g.L5 - 1 && spin < 2);
+  double2 v = make_double2(0.0, 0.0);
+  if (wall) {
+    const double2 x = q[r * V4 * 12 + i4 * 12 + G.perm[spin] * 3 + colour];
+    switch (G.phase[spin] & 3) {
+      case 0: v = x; break;
+      case 1: v = make_double2(-x.y, x.x); break;   // i x
+      case 2: v = make_double2(-x.x, -x.y); break;  // -x
+      default: v = make_double2(x.y, -x.x); break;  // -i x
+    }
+  }
+  eta[(r * g.L5 + s) * V4 * 12 + idx] = v;
+}
+
+// The gamma matrices (chiral DeGrand-Rossi basis, mu = x, y, z, t) as signed
+// permutations: row a of g_mu has its one entry i^ph[mu][a] in column col[mu][a].
+static const int kGammaCol[4][4] = {{3, 2, 1, 0}, {3, 2, 1, 0}, {2, 3, 0, 1}, {2, 3, 0, 1}};
+static const int kGammaPh[4][4] = {{1, 1, 3, 3}, {2, 0, 0, 2}, {1, 3, 3, 1}, {0, 0, 0, 0}};
+
+// Gamma = g_x^b0 g_y^b1 g_z^b2 g_t^b3 for mask = b0 + 2 b1 + 4 b2 + 8 b3.
+// (A B) has row a in column colB[colA[a]] with phase phA[a] + phB[colA[a]].
+static SpinPerm gamma_perm(int mask) {
+  SpinPerm G;
+  for (int a = 0; a < 4; ++a) {
+    G.perm[a] = a;
+    G.phase[a] = 0;
+  }
+  for (int mu = 0; mu < 4; ++mu) {
+    if (!((mask >> mu) & 1)) continue;
+    SpinPerm P;
+    for (int a = 0; a < 4; ++a) {
+      const int j = G.perm[a];
+      P.perm[a] = kGammaCol[mu][j];
+      P.phase[a] = (G.phase[a] + kGammaPh[mu][j]) & 3;
+    }
+    G = P;
+  }
+  return G;
+}
+
+hipError_t propagator_4d(const Geom& g, int nrhs, const double* psi, double* q, hipStream_t st) {
+  const size_t n = (size_t)g.Vh * 2 * 12;
+  const dim3 grid((unsigned)((n + 255) / 256), (unsigned)nrhs), blk(256);
+  return launch_k(k_propagator_4d, grid, blk, 0, st, g, reinterpret_cast<const double2*>(psi),
+                  reinterpret_cast<double2*>(q));
+}
+
+hipError_t current_source(const Geom& g, int nrhs, int mask, const double* q, double* eta, hipStream_t st) {
+  const size_t n = (size_t)g.Vh * 2 * 12;
+  const dim3 grid((unsigned)((n + 255) / 256), (unsigned)g.L5, (unsigned)nrhs), blk(256);
+  return launch_k(k_current_source, grid, blk, 0, st, g, gamma_perm(mask), reinterpret_cast<const double2*>(q),
+                  reinterpret_cast<double2*>(eta));
+}
+
 hipError_t layout_user_to_half(const Geom& g, const char* const* user, char* const* half, int par, int p,
                                int nslots, hipStream_t st) {
   const dim3 grid((g.Vh + 255) / 256, g.L5, nslots), blk(256);

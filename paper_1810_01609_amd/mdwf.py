@@ -106,6 +106,8 @@ _SIGS = {
     "mdwf_gauge_bytes": (ctypes.c_size_t, [_P]),
     "mdwf_source_point": (_I, [_P, ctypes.POINTER(Action), ctypes.POINTER(_I), _I, _I, _P]),
     "mdwf_source_z2": (_I, [_P, ctypes.POINTER(Action), ctypes.c_uint64, _I, _P]),
+    "mdwf_propagator_4d": (_I, [_P, ctypes.POINTER(Action), _I, _P, _P]),
+    "mdwf_current_source": (_I, [_P, ctypes.POINTER(Action), _I, _I, _P, _P]),
     "mdwf_dslash": (_I, [_P, _P, ctypes.POINTER(Action), _I, _I, _I, _P, _P]),
     "mdwf_solve": (_I, [_P, _P, ctypes.POINTER(Action), ctypes.POINTER(CGOpts), _I, _P, _P,
                         ctypes.POINTER(CGStats)]),
@@ -248,6 +250,22 @@ class Context:
         st = lib().mdwf_source_z2(self._h, ctypes.byref(act), ctypes.c_uint64(int(seed)), int(rhs_index),
                                   _ptr(eta, nb, "eta"))
         self._check(st, "mdwf_source_z2")
+
+    # ---- Feynman-Hellmann sequential source ----
+    def propagator_4d(self, act: Action, psi, q, nrhs: int = 1):
+        """q = P- psi_0 + P+ psi_{L5-1} (device tensors: psi in the 5D user
+        layout, q complex128 [rhs][t][z][y][x][4][3])."""
+        n4 = _numel(act) // act.L5
+        st = lib().mdwf_propagator_4d(self._h, ctypes.byref(act), int(nrhs), _ptr(psi, 16 * _numel(act) * nrhs, "psi"),
+                                      _ptr(q, 16 * n4 * nrhs, "q"))
+        self._check(st, "mdwf_propagator_4d")
+
+    def current_source(self, act: Action, gamma_mask: int, q, eta, nrhs: int = 1):
+        """eta = wall injection of Gamma q, Gamma = g_x^b0 g_y^b1 g_z^b2 g_t^b3."""
+        n4 = _numel(act) // act.L5
+        st = lib().mdwf_current_source(self._h, ctypes.byref(act), int(nrhs), int(gamma_mask),
+                                       _ptr(q, 16 * n4 * nrhs, "q"), _ptr(eta, 16 * _numel(act) * nrhs, "eta"))
+        self._check(st, "mdwf_current_source")
 
     # ---- operators ----
     def dslash(self, gauge, act: Action, op: int, prec, inp, out, nrhs: int = 1):

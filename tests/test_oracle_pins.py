@@ -358,3 +358,56 @@ def test_sampled_dirac_matches_full():
     got = O.dirac_at_sites(U, psi, act, sites)
     for k, (s, t, z, y, x) in enumerate(sites):
         assert _rel(got[k], full[s, t, z, y, x]) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# Feynman-Hellmann sequential propagator (P14-P16).
+# --------------------------------------------------------------------------
+def test_gamma_products_clifford():
+    """The 16 products of gamma matrices: mask 15 is the chiral gamma5
+    diag(1,1,-1,-1) written out, each squares to +-1, and they are
+    orthogonal, Tr(G_a^dag G_b) = 4 delta_ab (a basis of 4x4 matrices)."""
+    assert np.array_equal(O.gamma_product(15), np.diag([1, 1, -1, -1]).astype(np.complex128))
+    assert np.array_equal(O.gamma_product(0), np.eye(4, dtype=np.complex128))
+    Gs = [O.gamma_product(m) for m in range(16)]
+    for m, G in enumerate(Gs):
+        sq = G @ G
+        assert np.allclose(sq, np.eye(4)) or np.allclose(sq, -np.eye(4)), m
+        # a signed permutation with entries in {+-1, +-i}
+        assert np.count_nonzero(G) == 4 and np.allclose(np.abs(G[G != 0]), 1.0)
+    T = np.array([[np.trace(a.conj().T @ b) for b in Gs] for a in Gs])
+    assert np.allclose(T, 4 * np.eye(16))
+    # single gammas are the basis matrices themselves
+    for mu in range(4):
+        assert np.array_equal(O.gamma_product(1 << mu), O.GAMMA[mu])
+
+
+def test_propagator_4d_inverts_wall_injection():
+    """Reading the walls back, q = P- eta_0 + P+ eta_{L5-1}, returns the 4D
+    field a source was made from (for L5 = 1 as well)."""
+    for L5 in (1, 2, 5):
+        act = _act(L=(2, 2, 2, 4), L5=L5)
+        xi = S.random_spinor(act.L, 1, 3)[0]
+        assert np.array_equal(O.propagator_4d(O.wall_inject(xi, act), act), xi)
+
+
+@pytest.mark.parametrize("mask", [0, 11, 15])
+def test_feynman_hellmann_derivative(mask):
+    """The Feynman-Hellmann theorem on a 2^3x4, L5=4 lattice: with the current
+    J = inject o Gamma o extract added to the action, D(l) = D + l J,
+    d/dl D(l)^-1 eta = -D^-1 J D^-1 eta.  The central difference of dense
+    solves at l = +-1e-5 equals minus the sequential propagator; the
+    even-odd CG of fh_solve equals the dense sequential solve."""
+    act = _act(L=(2, 2, 2, 4), L5=4)
+    U = S.gauge_field(act.L, 0.3, 2)
+    shape = act.shape5
+    Dm = O.dense_matrix(lambda v: O.dirac(U, v, act), shape)
+    Jm = O.dense_matrix(lambda v: O.fh_operator(v, act, mask), shape)
+    eta = O.point_source(act, (0, 0, 0, 0), 1, 2).ravel()
+    psi = np.linalg.solve(Dm, eta)
+    psi_fh = np.linalg.solve(Dm, Jm @ psi)
+    lam = 1e-5
+    fd = (np.linalg.solve(Dm + lam * Jm, eta) - np.linalg.solve(Dm - lam * Jm, eta)) / (2 * lam)
+    assert _rel(-fd, psi_fh) < 1e-7
+    got, _ = O.fh_solve(U, psi.reshape(shape), act, mask, tol=1e-13)
+    assert _rel(got.ravel(), psi_fh) < 1e-10
