@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("dslash.hip", "dev_common.h", "kernels.h"):
+    for f in ("dslash.hip", "dev_common.h"):
         with open(os.path.join(ROOT, "paper_1810_01609_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
