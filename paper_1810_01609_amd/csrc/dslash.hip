@@ -480,123 +480,11 @@ __device__ __forceinline__ void hop_dir_single(const DslashArgs& A, const FieldD
 }
 
 
-// Both neighbours of direction mu (forward and backward) loaded before either
-// is used: two spinor loads in flight per thread instead of one.  Links come
-// from the LDS stage in the compute phase, so only the spinors are buffered.
-template <int P, bool DAG, bool PRO, int MU>
-__device__ __forceinline__ void hop_dir_pair(const DslashArgs& A, const FieldDesc& f, const char* in, int s,
-                                             const Coef5& c, Cplx<typename PrecTraits<P>::Real> acc[4][3],
-                                             Stage<typename PrecTraits<P>::Real> st, int CB, int cbl) {
-  using R = typename PrecTraits<P>::Real;
-  const Geom& g = A.g;
-  constexpr int SF = DAG ? +1 : -1;
-  constexpr int SB = -SF;
-  R v0[24], v1[24];
-  const int e0 = stage_nbr(st.nbr, MU, cbl);
-  const int e1 = stage_nbr(st.nbr, MU + 4, cbl);
-  if constexpr (PRO) {
-    load_bidiag<P>(in, f, e0, s, g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v0);
-    load_bidiag<P>(in, f, e1, s, g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v1);
-  } else {
-    SpinorIO<P>::load(in, f, e0, s, v0);
-    SpinorIO<P>::load(in, f, e1, s, v1);
-  }
-  Cplx<R> U[3][3], psi[4][3], h[2][3], w[2][3];
-#pragma unroll
-  for (int fb = 0; fb < 2; ++fb) {
-    const R* v = fb == 0 ? v0 : v1;
-    stage_link(st, MU + 4 * fb, CB, cbl, U);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = {v[2 * k], v[2 * k + 1]};
-    if (fb == 0) project<MU, SF>(psi, h);
-    else project<MU, SB>(psi, h);
-    if (fb == 0) {
-      colour_mul<false>(U, h, w);
-      accumulate<MU, SF>(acc, w);
-    } else {
-      colour_mul<true>(U, h, w);
-      accumulate<MU, SB>(acc, w);
-    }
-  }
-  pin_acc(acc);
-}
-
-// Software-pipelined hop over the 8 neighbours (mu forward, mu backward, ...):
-// the spinor of neighbour k+1 is requested before neighbour k is computed, so
-// each thread always has one neighbour load in flight behind its arithmetic.
-// Links and neighbour indices come from the LDS stage.
-template <int P, bool PRO>
-__device__ __forceinline__ void pipe_load(const DslashArgs& A, const FieldDesc& f, const char* in, int s,
-                                          const Coef5& c, int e, typename PrecTraits<P>::Real v[24]) {
-  using R = typename PrecTraits<P>::Real;
-  if constexpr (PRO) load_bidiag<P>(in, f, e, s, A.g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v);
-  else SpinorIO<P>::load(in, f, e, s, v);
-}
-
-template <int P, bool DAG, int K>
-__device__ __forceinline__ void pipe_compute(const typename PrecTraits<P>::Real v[24],
-                                             Cplx<typename PrecTraits<P>::Real> acc[4][3],
-                                             Stage<typename PrecTraits<P>::Real> st, int CB, int cbl) {
-  using R = typename PrecTraits<P>::Real;
-  constexpr int MU = K >> 1;
-  constexpr int FB = K & 1;  // 0 forward, 1 backward
-  constexpr int SF = DAG ? +1 : -1;
-  constexpr int SIG = FB == 0 ? SF : -SF;
-  Cplx<R> U[3][3], psi[4][3], h[2][3], w[2][3];
-  stage_link(st, MU + 4 * FB, CB, cbl, U);
-#pragma unroll
-  for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = {v[2 * k], v[2 * k + 1]};
-  project<MU, SIG>(psi, h);
-  colour_mul<FB == 1>(U, h, w);
-  accumulate<MU, SIG>(acc, w);
-}
-
-template <int P, bool DAG, bool PRO, int K>
-__device__ __forceinline__ void pipe_step(const DslashArgs& A, const FieldDesc& f, const char* in, int s,
-                                          const Coef5& c, Cplx<typename PrecTraits<P>::Real> acc[4][3],
-                                          Stage<typename PrecTraits<P>::Real> st, int CB, int cbl,
-                                          typename PrecTraits<P>::Real cur[24], typename PrecTraits<P>::Real nxt[24]) {
-  // neighbour order K = 2*mu + fb; stage index = mu + 4*fb
-  if constexpr (K < 7) {
-    constexpr int K1 = K + 1;
-    const int e1 = stage_nbr(st.nbr, (K1 >> 1) + 4 * (K1 & 1), cbl);
-    pipe_load<P, PRO>(A, f, in, s, c, e1, nxt);
-  }
-  pipe_compute<P, DAG, K>(cur, acc, st, CB, cbl);
-  pin_acc(acc);
-}
-
-template <int P, bool DAG, bool PRO>
-__device__ __forceinline__ void hop_pipelined(const DslashArgs& A, const FieldDesc& f, const char* in, int s,
-                                              const Coef5& c, Cplx<typename PrecTraits<P>::Real> acc[4][3],
-                                              Stage<typename PrecTraits<P>::Real> st, int CB, int cbl) {
-  using R = typename PrecTraits<P>::Real;
-  R a[24], b[24];
-  pipe_load<P, PRO>(A, f, in, s, c, stage_nbr(st.nbr, 0, cbl), a);
-  pipe_step<P, DAG, PRO, 0>(A, f, in, s, c, acc, st, CB, cbl, a, b);
-  pipe_step<P, DAG, PRO, 1>(A, f, in, s, c, acc, st, CB, cbl, b, a);
-  pipe_step<P, DAG, PRO, 2>(A, f, in, s, c, acc, st, CB, cbl, a, b);
-  pipe_step<P, DAG, PRO, 3>(A, f, in, s, c, acc, st, CB, cbl, b, a);
-  pipe_step<P, DAG, PRO, 4>(A, f, in, s, c, acc, st, CB, cbl, a, b);
-  pipe_step<P, DAG, PRO, 5>(A, f, in, s, c, acc, st, CB, cbl, b, a);
-  pipe_step<P, DAG, PRO, 6>(A, f, in, s, c, acc, st, CB, cbl, a, b);
-  pipe_step<P, DAG, PRO, 7>(A, f, in, s, c, acc, st, CB, cbl, b, a);
-}
-
-#ifndef MDWF_HOP_PIPE
-#define MDWF_HOP_PIPE 0
-#endif
-
-#ifndef MDWF_HOP_PAIR
-#define MDWF_HOP_PAIR 0
-#endif
-
 template <int P, bool DAG, bool PRO, bool STAGE, int MU>
 __device__ __forceinline__ void hop_dir(const DslashArgs& A, const FieldDesc& f, const char* in, int cb, int s,
                                         const int X[4], const Coef5& c, Cplx<typename PrecTraits<P>::Real> acc[4][3],
                                         Stage<typename PrecTraits<P>::Real> st, int CB, int cbl) {
   if constexpr (STAGE && Packed<P>::enabled) hop_dir_packed<P, DAG, PRO, MU>(A, f, in, s, c, acc, st, CB, cbl);
-  else if constexpr (STAGE && MDWF_HOP_PAIR) hop_dir_pair<P, DAG, PRO, MU>(A, f, in, s, c, acc, st, CB, cbl);
   else hop_dir_single<P, DAG, PRO, STAGE, MU>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
 }
 
@@ -803,14 +691,10 @@ __global__ __launch_bounds__(kMaxThreads<P>) MDWF_OCC void dslash5_kernel(Dslash
 #pragma unroll
         for (int b = 0; b < 3; ++b) acc[a][b] = {0, 0};
       const char* in = A.in[slot];
-      if constexpr (STAGE && MDWF_HOP_PIPE && !Packed<P>::enabled) {
-        hop_pipelined<P, DAG, PRO>(A, f, in, s, c, acc, st, CB, cbl);
-      } else {
-        hop_dir<P, DAG, PRO, STAGE, 0>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
-        hop_dir<P, DAG, PRO, STAGE, 1>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
-        hop_dir<P, DAG, PRO, STAGE, 2>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
-        hop_dir<P, DAG, PRO, STAGE, 3>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
-      }
+      hop_dir<P, DAG, PRO, STAGE, 0>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+      hop_dir<P, DAG, PRO, STAGE, 1>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+      hop_dir<P, DAG, PRO, STAGE, 2>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+      hop_dir<P, DAG, PRO, STAGE, 3>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
         v[2 * k] = acc[k / 3][k % 3].re;
