@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kBlasThreads) void k_cg_p(BlasArgs A) {
     SpinorIO<PS>::load(r, f, cb, s, rv);
 #pragma unroll
     for (int k = 0; k < 24; ++k) cur[k] = rv[k] + beta * cur[k];
-    SpinorIO<PS>::store(p, f, cb, s, cur);
+    SpinorIO<PS>::store(p, f, cb, s, cur, A.nt_store);
     if (s == 0) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) first_dn[k] = cur[12 + k];
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kBlasThreads) void k_cg_p(BlasArgs A) {
       // finish pt_{s-1}: spins 2,3 take c5 p_s
 #pragma unroll
       for (int k = 0; k < 12; ++k) pend[12 + k] += c5 * cur[12 + k];
-      SpinorIO<PS>::store(pt, f, cb, s - 1, pend);
+      SpinorIO<PS>::store(pt, f, cb, s - 1, pend, A.nt_store);
     }
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kBlasThreads) void k_cg_p(BlasArgs A) {
   }
 #pragma unroll
   for (int k = 0; k < 12; ++k) pend[12 + k] += wall * first_dn[k];
-  SpinorIO<PS>::store(pt, f, cb, L5 - 1, pend);
+  SpinorIO<PS>::store(pt, f, cb, L5 - 1, pend, A.nt_store);
 }
 
 template <int PI, int PO>

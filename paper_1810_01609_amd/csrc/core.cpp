@@ -316,6 +316,33 @@ static int traversal_bt(const Geom& g, int prec, int nslots) {
   return g.Lt % 2 == 0 ? 2 : 0;
 }
 
+// y-bands of the blocked traversal (MDWF_YB overrides; 1 = whole xy-planes).
+// An xy-plane of 32 or more 16-site workgroups is cut into bands of 4 y-rows:
+// on the 32^3 x 64 lattice (L5 = 12) this cut the stencil's time by 10 % (FP32)
+// and 3 % (FP16) for one right-hand side and by 24 % and 9 % for 12 fused
+// ones; 2-row and 1-row bands (12 right-hand sides) and 8-row bands (one)
+// gained less.  On
+// 24^3 x 64 (18 workgroups per plane) no band width gained more than the noise.
+static int traversal_yb(const Geom& g, int prec, int nslots) {
+  (void)prec, (void)nslots;
+  const char* e = getenv("MDWF_YB");
+  if (e != nullptr && e[0] != 0) return atoi(e);
+  if (g.Lxh * g.Ly < 32 * 16 || g.Ly % 4 != 0) return 1;
+  return g.Ly / 4;
+}
+
+// Streaming stores once the launch's output fields no longer fit the 256 MB
+// MALL together with the fields a CG iteration cycles through (MDWF_NT
+// overrides): +2-4 % on the stencil at 24^3 x 64 and 32^3 x 64; on 16^3 x 32
+// (37.7 MB per FP32 half-field) the fields stay cache-resident, and streaming
+// stores would evict them.
+int streaming_stores(const Geom& g, int prec, int nslots) {
+  const char* e = getenv("MDWF_NT");
+  if (e != nullptr && e[0] != 0) return atoi(e) != 0;
+  const double half = (double)g.Vh * g.L5 * spinor_site_bytes(prec);
+  return nslots * half > 48.0e6 ? 1 : 0;
+}
+
 static std::string tune_key(const Geom& g, int prec, const Prog& p, int nslots, bool cg) {
   char buf[256];
   snprintf(buf, sizeof(buf), "dslash5 p%d h%d d%d pr%d c%d.%d a%d r%d u%d s%d L%dx%dx%dx%d L5=%d n%d gfx950",
@@ -334,23 +361,47 @@ static int default_stage() {
   return (e != nullptr && e[0] == '0') ? 0 : 1;
 }
 
+// A candidate's code: log2 sites per workgroup (bits 0-7), LDS staging (bit
+// 8), and the traversal of the hop kernels: Bt + 1 (bits 12-15) and the y-band
+// count (bits 16-23), where 0 keeps the size-based default.  The traversal
+// only reorders whole workgroups, so every candidate gives the same result.
+constexpr int kTravBtShift = 12, kTravYbShift = 16;
+
 static void candidates(const Geom& g, int prec, DslashArgs A, bool hop, std::vector<int>& out, int& dflt) {
   out.clear();
   dflt = -1;
   const int stage = hop ? default_stage() : 0;
   A.stage = stage;
+  std::vector<int> trav{0};
+  if (hop) {
+    std::vector<int> ybs{1};
+    if (g.Ly % 4 == 0 && g.Ly / 4 > 1) ybs.push_back(g.Ly / 4);
+    for (int bt : {2, 4, 8}) {
+      if (g.Lt % bt != 0) continue;
+      for (int yb : ybs) trav.push_back(((bt + 1) << kTravBtShift) | (yb << kTravYbShift));
+    }
+  }
   for (int lg = 4; lg <= 7; ++lg) {
     const int CB = 1 << lg;
     if (CB * g.L5 > dslash_max_threads(prec)) break;
     if (CB > 2 * g.Vh && lg > 4) break;
     const size_t lds = dslash_lds_bytes(A, prec, lg, hop);
     if (lds > 160 * 1024) break;
-    out.push_back(lg | (stage << 8));
+    for (int t : trav) out.push_back(lg | (stage << 8) | t);
   }
   // untuned default: the smallest workgroup (16 sites x L5 slices) — it packs
   // the most resident waves per CU under the LDS and register limits, and the
-  // tuner picks it for nearly every kernel and lattice measured
+  // tuner picks it for nearly every kernel and lattice measured — with the
+  // size-based traversal
   if (!out.empty()) dflt = out.front();
+}
+
+static void apply_candidate(DslashArgs& A, int code) {
+  A.stage = (code >> 8) & 1;
+  const int bt1 = (code >> kTravBtShift) & 0xf;
+  const int yb = (code >> kTravYbShift) & 0xff;
+  if (bt1 != 0) A.order_bt = bt1 - 1;
+  if (yb != 0) A.order_yb = yb;
 }
 
 static double prog_bytes(const Geom& g, int prec, const Prog& p, int nslots, bool cg) {
@@ -387,6 +438,8 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int pre
   A.reduce = pr.reduce;
   A.coef_y = pr.coef;
   A.order_bt = traversal_bt(geom, prec, nslots);
+  A.order_yb = traversal_yb(geom, prec, nslots);
+  A.nt_store = streaming_stores(geom, prec, nslots);
   if (fuse != nullptr) {
     A.cg_update = 1;
     A.cg_x = fuse->x;
@@ -411,15 +464,17 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int pre
     (void)hipEventCreate(&e1);
     float best = 1e30f;
     int best_lg = dflt;
+    const DslashArgs A0 = A;
     for (int cl : cand) {
-      A.stage = cl >> 8;
-      hipError_t e = dslash_launch(A, prec, pr.hop, pr.dag, pr.pro, cl & 0xff, c->stream);  // warm-up
+      DslashArgs B = A0;
+      apply_candidate(B, cl);
+      hipError_t e = dslash_launch(B, prec, pr.hop, pr.dag, pr.pro, cl & 0xff, c->stream);  // warm-up
       if (e != hipSuccess) {
         (void)hipGetLastError();
         continue;
       }
       (void)hipEventRecord(e0, c->stream);
-      for (int r = 0; r < 3; ++r) (void)dslash_launch(A, prec, pr.hop, pr.dag, pr.pro, cl & 0xff, c->stream);
+      for (int r = 0; r < 3; ++r) (void)dslash_launch(B, prec, pr.hop, pr.dag, pr.pro, cl & 0xff, c->stream);
       (void)hipEventRecord(e1, c->stream);
       (void)hipEventSynchronize(e1);
       float ms = 0;
@@ -437,7 +492,7 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int pre
   }
   hipEvent_t ev;
   prof_begin(c, &ev);
-  A.stage = lg >> 8;
+  apply_candidate(A, lg);
   hipError_t e = dslash_launch(A, prec, pr.hop, pr.dag, pr.pro, lg & 0xff, c->stream);
   prof_end(c, cls, prog_bytes(geom, prec, pr, nslots, fuse != nullptr), ev);
   return e;
@@ -767,7 +822,8 @@ mdwf_status mdwf_tune_load(mdwf_ctx* c, const char* path) {
     int lg = -1;
     float ms = 0;
     rest >> lg >> ms;
-    if ((lg & 0xff) >= 4 && (lg & 0xff) <= 7 && (lg >> 8) <= 1) {
+    if ((lg & 0xff) >= 4 && (lg & 0xff) <= 7 && ((lg >> 9) & 7) == 0 && ((lg >> kTravBtShift) & 0xf) <= 9 &&
+        (lg >> 24) == 0) {
       c->tune[line.substr(0, bar)] = lg;
       c->tune_ms[line.substr(0, bar)] = ms;
     }

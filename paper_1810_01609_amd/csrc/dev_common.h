@@ -139,7 +139,12 @@ typedef unsigned v2u __attribute__((ext_vector_type(2)));
 #define MDWF_GLOBAL
 #endif
 template <class V> __device__ __forceinline__ V ldg(const void* p) { return *(const MDWF_GLOBAL V*)(p); }
-template <class V> __device__ __forceinline__ void stg(void* p, V v) { *(MDWF_GLOBAL V*)(p) = v; }
+// nt: a streaming (non-temporal) store, for fields the launch writes once and
+// no workgroup of it reads back: it keeps the caches for the neighbour reads.
+template <class V> __device__ __forceinline__ void stg(void* p, V v, bool nt = false) {
+  if (nt) __builtin_nontemporal_store(v, (MDWF_GLOBAL V*)(p));
+  else *(MDWF_GLOBAL V*)(p) = v;
+}
 
 // ---------------------------------------------------------------------------
 // complex arithmetic
@@ -238,10 +243,11 @@ template <> struct SpinorIO<F64> {
       v[2 * g + 1] = d.y;
     }
   }
-  static __device__ __forceinline__ void store(char* base, const FieldDesc& f, int cb, int s, const R v[24]) {
+  static __device__ __forceinline__ void store(char* base, const FieldDesc& f, int cb, int s, const R v[24],
+                                                bool nt = false) {
     double2* p = reinterpret_cast<double2*>(base) + tile_index(cb, s, 0, f.L5, 12);
 #pragma unroll
-    for (int g = 0; g < 12; ++g) stg<v2d>(p + (size_t)g * kSiteTile, v2d{v[2 * g], v[2 * g + 1]});
+    for (int g = 0; g < 12; ++g) stg<v2d>(p + (size_t)g * kSiteTile, v2d{v[2 * g], v[2 * g + 1]}, nt);
   }
 };
 
@@ -269,10 +275,11 @@ template <> struct SpinorIO<F32> {
       v[4 * g + 3] = d.w;
     }
   }
-  static __device__ __forceinline__ void store(char* base, const FieldDesc& f, int cb, int s, const R v[24]) {
+  static __device__ __forceinline__ void store(char* base, const FieldDesc& f, int cb, int s, const R v[24],
+                                                bool nt = false) {
     float4* p = reinterpret_cast<float4*>(base) + tile_index(cb, s, 0, f.L5, 6);
 #pragma unroll
-    for (int g = 0; g < 6; ++g) stg<v4f>(p + (size_t)g * kSiteTile, v4f{v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]});
+    for (int g = 0; g < 6; ++g) stg<v4f>(p + (size_t)g * kSiteTile, v4f{v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]}, nt);
   }
 };
 
@@ -333,7 +340,8 @@ template <int P> struct SpinorIO16 {
       for (int k = 0; k < 12; ++k) v[k] = t[k + 4];
     }
   }
-  static __device__ __forceinline__ void store(char* base, const FieldDesc& f, int cb, int s, const R v[24]) {
+  static __device__ __forceinline__ void store(char* base, const FieldDesc& f, int cb, int s, const R v[24],
+                                                bool nt = false) {
     float m = 0.f;
 #pragma unroll
     for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf(v[k]));
@@ -348,9 +356,9 @@ template <int P> struct SpinorIO16 {
       const R* w = v + 8 * g;
       const v4u q{pack2<P>(w[0] * inv, w[1] * inv), pack2<P>(w[2] * inv, w[3] * inv),
                   pack2<P>(w[4] * inv, w[5] * inv), pack2<P>(w[6] * inv, w[7] * inv)};
-      stg<v4u>(p + (size_t)g * kSiteTile, q);
+      stg<v4u>(p + (size_t)g * kSiteTile, q, nt);
     }
-    stg<float>(reinterpret_cast<float*>(base + half_scale_offset(f.L5, f.Vh)) + tile_scale_index(cb, s, f.L5), m);
+    stg<float>(reinterpret_cast<float*>(base + half_scale_offset(f.L5, f.Vh)) + tile_scale_index(cb, s, f.L5), m, nt);
   }
 };
 template <> struct SpinorIO<F16> : SpinorIO16<F16> {};

@@ -618,24 +618,29 @@ template <class R> __device__ __forceinline__ void lds_get(const R* lds, int CB,
 // ---------------------------------------------------------------------------
 // First site of workgroup q.  order_bt = 0: consecutive workgroups take
 // consecutive ranges of cb (t is the slowest index, so a site's t-neighbours
-// are a whole time slice away in the access stream).  order_bt = Bt > 0 (the
-// xy-plane holds a whole number of workgroups, Bt divides Lt): xy-planes are
-// visited in blocks of Bt time slices, z inside a block, t fastest, so the
-// z- and t-neighbour planes of a plane are at most Bt planes away and stay in
-// the XCD's L2.  Sites inside a plane stay consecutive (same reduction tiles).
+// are a whole time slice away in the access stream).  order_bt = Bt > 0 (Bt
+// divides Lt): the lattice is cut into order_yb bands of Ly/order_yb y-rows
+// (the band's xy-rectangle holds a whole number of workgroups); inside a band
+// the (z, t) rectangles are visited in blocks of Bt time slices, z inside a
+// block, t fastest.  The z- and t-neighbour rectangles of a rectangle are then
+// at most Bt rectangles away in the access stream, and a narrower band keeps
+// that distance (in bytes) inside the XCD's L2.  Sites inside a rectangle stay
+// consecutive (same reduction tiles).
 __device__ __forceinline__ int block_first_site(const DslashArgs& A, int q, int CB) {
   if (A.order_bt == 0) return q * CB;
   const Geom& g = A.g;
-  const int plane = g.Lxh * g.Ly;
-  const int bpp = plane / CB;  // workgroups per plane
+  const int rows = g.Ly / A.order_yb;
+  const int bpp = g.Lxh * rows / CB;  // workgroups per rectangle
   const int k = q % bpp;
   int r = q / bpp;
   const int tt = r % A.order_bt;
   r /= A.order_bt;
   const int z = r % g.Lz;
-  const int tb = r / g.Lz;
-  const int t = tb * A.order_bt + tt;
-  return (t * g.Lz + z) * plane + k * CB;
+  r /= g.Lz;
+  const int ntb = g.Lt / A.order_bt;
+  const int t = (r % ntb) * A.order_bt + tt;
+  const int yb = r / ntb;
+  return ((t * g.Lz + z) * g.Ly + yb * rows) * g.Lxh + k * CB;
 }
 
 // FP64 needs ~180 VGPRs per thread (2 waves per SIMD), the 32-bit
@@ -744,8 +749,8 @@ __global__ __launch_bounds__(kMaxThreads<P>) MDWF_OCC void dslash5_kernel(Dslash
         rv[k] -= alpha * v[k];
         v[k] = rv[k];
       }
-      SpinorIO<PX>::store(A.cg_x[slot], f, cb, s, xv);
-      SpinorIO<P>::store(A.cg_r[slot], f, cb, s, rv);
+      SpinorIO<PX>::store(A.cg_x[slot], f, cb, s, xv, A.nt_store);
+      SpinorIO<P>::store(A.cg_r[slot], f, cb, s, rv, A.nt_store);
     }
   }
 
@@ -782,7 +787,7 @@ __global__ __launch_bounds__(kMaxThreads<P>) MDWF_OCC void dslash5_kernel(Dslash
     __syncthreads();
     lds_get(lds, CB, cbl, s, v);
   }
-  if (valid && !CGU) SpinorIO<P>::store(A.out[slot], f, cb, s, v);
+  if (valid && !CGU) SpinorIO<P>::store(A.out[slot], f, cb, s, v, A.nt_store);
 }
 
 // ---------------------------------------------------------------------------
@@ -841,8 +846,8 @@ hipError_t dslash_launch(DslashArgs A, int prec, bool hop, bool dag, bool pro, i
   const int CB = 1 << cb_log2;
   A.cb_log2 = cb_log2;
   A.nblk = (A.g.Vh + CB - 1) / CB;
-  const int plane = A.g.Lxh * A.g.Ly;
-  if (A.order_bt > 0 && (plane % CB != 0 || A.g.Lt % A.order_bt != 0)) A.order_bt = 0;
+  if (A.order_yb < 1 || A.g.Ly % A.order_yb != 0 || (A.g.Lxh * (A.g.Ly / A.order_yb)) % CB != 0) A.order_yb = 1;
+  if (A.order_bt > 0 && ((A.g.Lxh * A.g.Ly) % CB != 0 || A.g.Lt % A.order_bt != 0)) A.order_bt = 0;
   size_t chain, red, stage;
   lds_layout(A, prec, cb_log2, hop, chain, red, stage);
   A.lds_chain_bytes = (int)std::max(chain, stage);  // offset of the reduction area

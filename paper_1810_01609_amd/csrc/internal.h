@@ -147,6 +147,9 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* g, const Geom& geom, int prec
                     char* const* in, char* const* aux, char* const* out, const Coef5* coef_d, int nslots,
                     const int* active, int active_stride, double* partials, int ntiles, int cls, bool tunable,
                     const CgFuse* fuse = nullptr);
+// 1 when a launch over nslots fields of this size should store with
+// streaming (non-temporal) writes
+int streaming_stores(const Geom& g, int prec, int nslots);
 void prof_begin(mdwf_ctx* c, hipEvent_t* e0);
 void prof_end(mdwf_ctx* c, int cls, double bytes, hipEvent_t e0);
 // CG loop accounting (see mdwf_ctx): a chunk of `chunk` iterations starts;

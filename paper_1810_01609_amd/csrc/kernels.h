@@ -71,6 +71,8 @@ struct DslashArgs {
   int lds_stage_off;       // filled by the launcher
   int stage;               // 1: stage neighbour indices and links in LDS once per workgroup
   int order_bt;            // > 0: blocked (z, t) plane traversal with Bt time slices per block
+  int order_yb;            // with order_bt > 0: the xy-plane is cut into order_yb bands of Ly/order_yb rows
+  int nt_store;            // 1: the launch's field stores are streaming (non-temporal)
   int c1, c2, aux_mode, reduce;
   double coef_y;
   // CG update fused into the epilogue (cg_update = 1): with q the combined
@@ -100,6 +102,7 @@ struct BlasArgs {
   int nslots;
   double ca, cb;    // coefficients for axpby
   const Coef5* coef; // [nslots] (k_cg_p)
+  int nt_store;      // k_cg_p: streaming stores of p and pt
 };
 constexpr int kBlasThreads = 256;
 

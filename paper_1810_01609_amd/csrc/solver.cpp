@@ -572,6 +572,7 @@ extern "C" mdwf_status mdwf_job_step(mdwf_ctx* c, mdwf_job* const* jobs, int32_t
         B.a = P; B.b = R; B.c = PT;
         B.st = S_d;
         B.coef = coef_d;
+        B.nt_store = streaming_stores(geom, ps, n);
         prof_begin(c, &ev);
         e = blas_cg_p(B, ps, c->stream);
         prof_end(c, MDWF_PROF_BLAS, n * ne * 4.0 * spinor_site_bytes(ps), ev);

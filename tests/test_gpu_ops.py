@@ -31,6 +31,8 @@ CASES = {
     "free": ((4, 4, 2, 4), 4, 0.1, 0.0, 0, 1),
     # xy-plane of 64 sites per parity: the blocked (z, t) traversal engages
     "blocked": ((16, 8, 4, 8), 4, 0.05, 0.3, 9, 1),
+    # xy-plane of 512 sites per parity: the traversal also cuts it into y-bands
+    "banded": ((32, 32, 2, 4), 2, 0.05, 0.3, 10, 1),
 }
 
 
@@ -150,6 +152,27 @@ def test_multi_rhs_dslash_matches_single(ctx):
         one = empty_like_dev(x.shape[1:])
         ctx.dslash(g, act, M.OP_NORMAL, "f64", to_dev(x[r]), one)
         assert np.array_equal(to_host(one), got[r])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_traversal_orders_bitwise(ctx, prec, monkeypatch):
+    """The workgroup traversal (linear, blocked in t, cut into y-bands) only
+    reorders whole workgroups: every order gives bitwise the same field."""
+    from paper_1810_01609_amd import mdwf as M
+
+    U, act, oact, g = _setup(ctx, "banded")
+    x = S.random_spinor(act.lattice, act.L5, 400)
+    outs = []
+    for bt, yb in ((0, 1), (2, 1), (4, 1), (2, 8), (4, 4), (4, 2)):
+        monkeypatch.setenv("MDWF_BT", str(bt))
+        monkeypatch.setenv("MDWF_YB", str(yb))
+        log(f"[op] traversal bt={bt} yb={yb} {prec}")
+        out = empty_like_dev(x.shape)
+        ctx.dslash(g, act, M.OP_NORMAL, prec, to_dev(x), out)
+        outs.append(to_host(out))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    assert rel(outs[0], _oracle("NORMAL", U, x, oact)) < TOL[prec]
 
 
 def test_gpu_identities(ctx):
