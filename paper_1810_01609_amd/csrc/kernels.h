@@ -20,13 +20,14 @@ struct LaunchTiming {
 };
 LaunchTiming& launch_timing();
 
+// A failed launch is left in the runtime's last-error state: every caller
+// returns hipGetLastError() after its launches.
 template <class F, class... Args>
-inline hipError_t launch_k(F kernel, dim3 grid, dim3 block, size_t smem, hipStream_t st, Args... args) {
+inline void launch_k(F kernel, dim3 grid, dim3 block, size_t smem, hipStream_t st, Args... args) {
   LaunchTiming& t = launch_timing();
   hipEvent_t e0 = (t.stop != nullptr && t.launches == 0) ? t.start : nullptr;
   hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)smem, st, e0, t.stop, 0u, args...);
   if (t.stop != nullptr) ++t.launches;
-  return hipGetLastError();
 }
 
 // Fifth-dimension chains applied to whole columns of a site.

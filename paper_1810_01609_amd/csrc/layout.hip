@@ -199,15 +199,17 @@ static SpinPerm gamma_perm(int mask) {
 hipError_t propagator_4d(const Geom& g, int nrhs, const double* psi, double* q, hipStream_t st) {
   const size_t n = (size_t)g.Vh * 2 * 12;
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)nrhs), blk(256);
-  return launch_k(k_propagator_4d, grid, blk, 0, st, g, reinterpret_cast<const double2*>(psi),
-                  reinterpret_cast<double2*>(q));
+  launch_k(k_propagator_4d, grid, blk, 0, st, g, reinterpret_cast<const double2*>(psi),
+           reinterpret_cast<double2*>(q));
+  return hipGetLastError();
 }
 
 hipError_t current_source(const Geom& g, int nrhs, int mask, const double* q, double* eta, hipStream_t st) {
   const size_t n = (size_t)g.Vh * 2 * 12;
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)g.L5, (unsigned)nrhs), blk(256);
-  return launch_k(k_current_source, grid, blk, 0, st, g, gamma_perm(mask), reinterpret_cast<const double2*>(q),
-                  reinterpret_cast<double2*>(eta));
+  launch_k(k_current_source, grid, blk, 0, st, g, gamma_perm(mask), reinterpret_cast<const double2*>(q),
+           reinterpret_cast<double2*>(eta));
+  return hipGetLastError();
 }
 
 hipError_t layout_user_to_half(const Geom& g, const char* const* user, char* const* half, int par, int p,
