@@ -65,12 +65,6 @@ mdwf_status check_action_msg(const mdwf_action* a, std::string& msg) {
     msg = "L5 must be in [1, 32]";
     return MDWF_EINVAL;
   }
-  // spinor fields are indexed in 16-byte units with 32-bit arithmetic: an
-  // FP64 half-field (12 units per 5D site, sites padded to 16) must fit
-  if ((std::floor(v4 / 2 / 16) + 1) * 16 * a->L5 * 12 >= 4294967296.0) {
-    msg = "lattice too large (an FP64 half-field must stay below 2^32 16-byte units)";
-    return MDWF_EINVAL;
-  }
   if (!std::isfinite(a->b5) || !std::isfinite(a->c5) || !std::isfinite(a->M5) || !std::isfinite(a->mq)) {
     msg = "b5, c5, M5, mq must be finite";
     return MDWF_EINVAL;

@@ -41,8 +41,6 @@ def test_abi_version():
         (dict(L=(4, 4, 4, 4), L5=4, mq=-0.1), "mq must be >= 0"),
         (dict(L=(4, 4, 4, 4), L5=4, b5=float("nan")), "finite"),
         (dict(L=(4, 4, 4, 4), L5=4, t_antiperiodic=2), "t_antiperiodic"),
-        # 64^3 x 128: 16.8 M sites per parity, x 24 slices x 12 FP64 units > 2^32
-        (dict(L=(64, 64, 64, 128), L5=24), "2^32 16-byte units"),
     ],
 )
 def test_check_action_rejects(kw, frag):
@@ -50,11 +48,6 @@ def test_check_action_rejects(kw, frag):
     st, msg = M.check_action(act)
     assert st == M.EINVAL
     assert frag in msg
-
-
-def test_check_action_accepts_largest_indexable_field():
-    # 16.8 M sites per parity x 16 slices x 12 FP64 units = 3.2e9 < 2^32
-    assert M.check_action(M.Action.make((64, 64, 64, 128), 16)) == (M.OK, "")
 
 
 def test_check_action_accepts_benchmark_configs():
