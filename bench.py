@@ -171,6 +171,63 @@ def fh_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def split_bench(args):
+    """One rank's share of a domain-decomposed hop: the workload's lattice cut
+    in two along y, z and t (the 2x2x2 split of eight GPUs), the local block
+    computed with its faces packed, the interior hop, and the exterior update
+    from the faces (the lattice is its own neighbour: the exchange over xGMI is
+    what one GPU cannot show, so its time is projected from the face bytes)."""
+    import torch
+
+    import mdwf_synth as S
+    from paper_1810_01609_amd import mdwf as M
+
+    cfg = S.CONFIGS[args.workload]
+    Lg, L5 = cfg["L"], cfg["L5"]
+    mask = 0b1110
+    L = tuple(n // 2 if (mask >> m) & 1 else n for m, n in enumerate(Lg))
+    act = M.Action.make(L, L5, cfg["b5"], cfg["c5"], cfg["M5"], cfg["mq"])
+    ctx = M.Context(0)
+    U = S.gauge_field(L, cfg["eps"], cfg["seed"])
+    precs = args.precs.split(",")
+    g = ctx.gauge_load(L, U, precs=tuple(dict.fromkeys(["f64"] + precs)))
+    del U
+    x = torch.zeros(act.spinor_shape(), dtype=torch.complex128, device="cuda")
+    ctx.source_z2(act, 7, 0, x)
+    y = torch.zeros_like(x)
+    vh = L[0] * L[1] * L[2] * L[3] // 2
+    out = {}
+    for p in precs:
+        rb = 8 if p == "f64" else 4
+        face = {m: 2 * (vh * 2 // L[m] // 2) * L5 * 12 * rb for m in range(4) if (mask >> m) & 1}
+        res = {}
+        for name, m in (("plain", 0), ("split", mask)):
+            for _ in range(2):
+                ctx.hop_split(g, act, p, m, x, y)
+            ctx.profile_enable(True)
+            ctx.profile_reset()
+            ph = [0.0, 0.0, 0.0]
+            for _ in range(args.steps):
+                t = ctx.hop_split(g, act, p, m, x, y, timed=True)
+                ph = [a + b for a, b in zip(ph, t)]
+            d = ctx.profile_read(M.PROF_DSLASH_F64 if p == "f64" else M.PROF_DSLASH_INNER)
+            ctx.profile_enable(False)
+            ph = [v / args.steps for v in ph]
+            res[name] = {"pack_ms": ph[0], "hop_ms": ph[1], "exterior_ms": ph[2],
+                         "hop_GB_per_s": d["bytes"] / (d["ms"] * 1e-3) / 1e9}
+        link_gbs = 153.0
+        res["face_bytes_per_peer"] = face
+        res["xgmi_ms_per_peer_link"] = {m: b / (link_gbs * 1e9) * 1e3 for m, b in face.items()}
+        res["split_total_ms"] = res["split"]["pack_ms"] + res["split"]["hop_ms"] + res["split"]["exterior_ms"]
+        res["overhead_vs_plain"] = res["split_total_ms"] / res["plain"]["hop_ms"] - 1.0
+        out[p] = res
+    g.free()
+    ctx.close()
+    print(json.dumps({"workload": f"{args.workload} split 2x2x2 in (y, z, t): one rank's block",
+                      "local_lattice": list(L), "L5": L5, "split_mask": mask, "steps": args.steps,
+                      "xgmi_link_GB_per_s": 153.0, "hop": out}), flush=True)
+
+
 def serve_bench(args):
     """c5: a Poisson stream of solves served with continuous batching."""
     import mdwf_synth as S
@@ -296,6 +353,9 @@ def main():
                          "last (default by inner precision: 0.01 for f32, 0.1 for 16-bit)")
     ap.add_argument("--check-every", type=int, default=8, help="CG iterations between host polls of the solver state")
     ap.add_argument("--fh", action="store_true", help="Feynman-Hellmann propagator pairs instead of single solves")
+    ap.add_argument("--split", action="store_true",
+                    help="one rank's share of the workload split 2x2x2 in (y, z, t): face packing, interior and "
+                         "exterior hop against the plain hop of the same block")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time the solves without per-launch HIP events (no roofline figures)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -323,6 +383,9 @@ def main():
         return
     if args.fh:
         fh_bench(args)
+        return
+    if args.split:
+        split_bench(args)
         return
     if args.dslash_only:
         dslash_bench(args)

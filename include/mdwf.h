@@ -226,6 +226,30 @@ MDWF_API mdwf_status mdwf_current_source(mdwf_ctx *ctx, const mdwf_action *act, 
 MDWF_API mdwf_status mdwf_dslash(mdwf_ctx *ctx, const mdwf_gauge *g, const mdwf_action *act, int32_t op, int32_t prec,
                         int32_t nrhs, const void *in, void *out);
 
+/* out_e = H_eo in_o (as MDWF_OP_HOP_EO; the odd parity of out is set to zero)
+ * computed the way one rank of a 4D domain-decomposed run computes it (paper,
+ * "Current State of the Art": pack the halo, communicate it, apply the
+ * interior stencil, then complete the halo part).  Bit mu of split_mask
+ * (0..15) marks dimension mu as split between ranks; the lattice is its own
+ * neighbour in each split dimension, so the faces a neighbour would send are
+ * the ones this call packs.  Steps: (1) pack, per split mu, the spin-projected
+ * half spinors (12 reals per site and slice) of the odd sites with x_mu = 0
+ * (projector 1 - g_mu) and, already multiplied by U_mu^+, of those with
+ * x_mu = L_mu - 1 (projector 1 + g_mu), in the arithmetic precision of prec
+ * (FP64 for MDWF_F64, FP32 otherwise); (2) the fused stencil over all even
+ * sites without the hops that cross a split boundary; (3) add those hops from
+ * the packed faces (the forward ones multiplied by the site's own link, the
+ * antiperiodic sign at the t boundary).  split_mask = 0 is MDWF_OP_HOP_EO.
+ * Split dimensions need even extents, and splitting x needs an even Ly.  The
+ * face buffers live in the context's workspace.  in, out: device, user
+ * layout, nrhs fields, not overlapping.  phase_ms: NULL, or 3 doubles that
+ * receive the GPU time of (1), (2) and (3) in milliseconds (the call then
+ * waits for the stream).  Asynchronous on the context stream otherwise.
+ * Errors: MDWF_EINVAL for a bad mask, extent or argument, MDWF_EHIP for a
+ * failed launch. */
+MDWF_API mdwf_status mdwf_hop_split(mdwf_ctx *ctx, const mdwf_gauge *g, const mdwf_action *act, int32_t prec,
+                                    int32_t split_mask, int32_t nrhs, const void *in, void *out, double *phase_ms);
+
 /* ---- propagator solve ----------------------------------------------------- */
 
 /* psi = D^-1 eta for nrhs right-hand sides, by even-odd CG on the normal

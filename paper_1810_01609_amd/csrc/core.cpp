@@ -348,7 +348,9 @@ static std::string tune_key(const Geom& g, int prec, const Prog& p, int nslots, 
   snprintf(buf, sizeof(buf), "dslash5 p%d h%d d%d pr%d c%d.%d a%d r%d u%d s%d L%dx%dx%dx%d L5=%d n%d gfx950",
            prec, (int)p.hop, (int)p.dag, (int)p.pro, p.c1, p.c2, p.aux, p.reduce, (int)cg,
            p.hop ? default_stage() : 0, g.Lx, g.Ly, g.Lz, g.Lt, g.L5, nslots);
-  return buf;
+  std::string k = buf;
+  if (p.split != 0) k += " x" + std::to_string(p.split);
+  return k;
 }
 
 // Launch candidates: log2 of sites per workgroup (bits 0-7); bit 8 carries
@@ -440,6 +442,7 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int pre
   A.order_bt = traversal_bt(geom, prec, nslots);
   A.order_yb = traversal_yb(geom, prec, nslots);
   A.nt_store = streaming_stores(geom, prec, nslots);
+  A.split_mask = pr.split;
   if (fuse != nullptr) {
     A.cg_update = 1;
     A.cg_x = fuse->x;

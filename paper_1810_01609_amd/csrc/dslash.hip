@@ -277,7 +277,9 @@ __host__ __device__ __forceinline__ size_t stage_nbr_bytes(int CB) {
   return round_up((size_t)CB * kStageNbrStride * sizeof(int), 16);
 }
 
-template <int P>
+// SPLIT: a hop across the boundary of a split dimension is staged with
+// neighbour index -1 (and a zero link); the hop skips it.
+template <int P, bool SPLIT>
 __device__ __forceinline__ void stage_fill(const DslashArgs& A, Stage<typename PrecTraits<P>::Real> st, int CB,
                                            int cb_log2, int cb0, int tid, int nthr) {
   using R = typename PrecTraits<P>::Real;
@@ -296,7 +298,10 @@ __device__ __forceinline__ void stage_fill(const DslashArgs& A, Stage<typename P
       site_coords(g, A.out_par, cb, X[0], X[1], X[2], X[3]);
       const int mu = dir & 3;
       const int Lmu = mu == 0 ? g.Lx : mu == 1 ? g.Ly : mu == 2 ? g.Lz : g.Lt;
-      if (dir < 4) {
+      const bool cut = SPLIT && ((A.split_mask >> mu) & 1) && (dir < 4 ? X[mu] + 1 == Lmu : X[mu] == 0);
+      if (cut) {
+        nb = -1;
+      } else if (dir < 4) {
         flip = mu == 3 && g.tap && X[3] == g.Lt - 1;
         X[mu] = X[mu] + 1 == Lmu ? 0 : X[mu] + 1;
         nb = cb_index(g, X[0], X[1], X[2], X[3]);
@@ -363,7 +368,7 @@ __device__ __forceinline__ float load_bidiag_norm(const char* base, const FieldD
   return m;
 }
 
-template <int P, bool DAG, bool PRO, int MU>
+template <int P, bool DAG, bool PRO, int MU, bool SPLIT>
 __device__ __forceinline__ void hop_dir_packed(const DslashArgs& A, const FieldDesc& f, const char* in, int s,
                                                const Coef5& c, Cplx<float> acc[4][3], Stage<float> st, int CB,
                                                int cbl) {
@@ -375,6 +380,9 @@ __device__ __forceinline__ void hop_dir_packed(const DslashArgs& A, const FieldD
 #pragma unroll
   for (int fb = 0; fb < 2; ++fb) {
     const int nb = stage_nbr(st.nbr, MU + 4 * fb, cbl);
+    if constexpr (SPLIT) {
+      if (nb < 0) continue;
+    }
     T2 h[2][3];
     float sc;
     if constexpr (PRO) {
@@ -406,7 +414,7 @@ __device__ __forceinline__ void hop_dir_packed(const DslashArgs& A, const FieldD
   }
 }
 
-template <int P, bool DAG, bool PRO, bool STAGE, int MU>
+template <int P, bool DAG, bool PRO, bool STAGE, int MU, bool SPLIT>
 __device__ __forceinline__ void hop_dir_single(const DslashArgs& A, const FieldDesc& f, const char* in, int cb, int s,
                                         const int X[4], const Coef5& c, Cplx<typename PrecTraits<P>::Real> acc[4][3],
                                         Stage<typename PrecTraits<P>::Real> st, int CB, int cbl) {
@@ -424,6 +432,9 @@ __device__ __forceinline__ void hop_dir_single(const DslashArgs& A, const FieldD
     bool flip;
     if constexpr (STAGE) {
       nb = stage_nbr(st.nbr, MU + 4 * fb, cbl);
+      if constexpr (SPLIT) {
+        if (nb < 0) continue;
+      }
       flip = false;  // carried by the staged link
       stage_link(st, MU + 4 * fb, CB, cbl, U);
     } else {
@@ -480,12 +491,12 @@ __device__ __forceinline__ void hop_dir_single(const DslashArgs& A, const FieldD
 }
 
 
-template <int P, bool DAG, bool PRO, bool STAGE, int MU>
+template <int P, bool DAG, bool PRO, bool STAGE, int MU, bool SPLIT>
 __device__ __forceinline__ void hop_dir(const DslashArgs& A, const FieldDesc& f, const char* in, int cb, int s,
                                         const int X[4], const Coef5& c, Cplx<typename PrecTraits<P>::Real> acc[4][3],
                                         Stage<typename PrecTraits<P>::Real> st, int CB, int cbl) {
-  if constexpr (STAGE && Packed<P>::enabled) hop_dir_packed<P, DAG, PRO, MU>(A, f, in, s, c, acc, st, CB, cbl);
-  else hop_dir_single<P, DAG, PRO, STAGE, MU>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+  if constexpr (STAGE && Packed<P>::enabled) hop_dir_packed<P, DAG, PRO, MU, SPLIT>(A, f, in, s, c, acc, st, CB, cbl);
+  else hop_dir_single<P, DAG, PRO, STAGE, MU, SPLIT>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
 }
 
 // ---------------------------------------------------------------------------
@@ -656,7 +667,7 @@ template <int P> constexpr int kMaxThreads = P == F64 ? 512 : 1024;
 #define MDWF_OCC
 #endif
 
-template <int P, bool HOP, bool DAG, bool PRO, bool STAGE, bool CGU>
+template <int P, bool HOP, bool DAG, bool PRO, bool STAGE, bool CGU, bool SPLIT>
 __global__ __launch_bounds__(kMaxThreads<P>) MDWF_OCC void dslash5_kernel(DslashArgs A) {
   using R = typename PrecTraits<P>::Real;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -679,7 +690,7 @@ __global__ __launch_bounds__(kMaxThreads<P>) MDWF_OCC void dslash5_kernel(Dslash
   Stage<R> st{reinterpret_cast<int*>(smem + A.lds_stage_off),
               reinterpret_cast<R*>(smem + A.lds_stage_off + stage_nbr_bytes(CB))};
   if constexpr (HOP && STAGE) {
-    stage_fill<P>(A, st, CB, A.cb_log2, cb0, tid, nthr);
+    stage_fill<P, SPLIT>(A, st, CB, A.cb_log2, cb0, tid, nthr);
     __syncthreads();
   }
 
@@ -696,10 +707,10 @@ __global__ __launch_bounds__(kMaxThreads<P>) MDWF_OCC void dslash5_kernel(Dslash
 #pragma unroll
         for (int b = 0; b < 3; ++b) acc[a][b] = {0, 0};
       const char* in = A.in[slot];
-      hop_dir<P, DAG, PRO, STAGE, 0>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
-      hop_dir<P, DAG, PRO, STAGE, 1>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
-      hop_dir<P, DAG, PRO, STAGE, 2>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
-      hop_dir<P, DAG, PRO, STAGE, 3>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+      hop_dir<P, DAG, PRO, STAGE, 0, SPLIT>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+      hop_dir<P, DAG, PRO, STAGE, 1, SPLIT>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+      hop_dir<P, DAG, PRO, STAGE, 2, SPLIT>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
+      hop_dir<P, DAG, PRO, STAGE, 3, SPLIT>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
         v[2 * k] = acc[k / 3][k % 3].re;
@@ -793,9 +804,9 @@ __global__ __launch_bounds__(kMaxThreads<P>) MDWF_OCC void dslash5_kernel(Dslash
 // ---------------------------------------------------------------------------
 // launcher
 // ---------------------------------------------------------------------------
-template <int P, bool HOP, bool DAG, bool PRO, bool STAGE, bool CGU = false>
+template <int P, bool HOP, bool DAG, bool PRO, bool STAGE, bool CGU = false, bool SPLIT = false>
 static hipError_t launch_t(const DslashArgs& A, int threads, size_t smem, int grid, hipStream_t st) {
-  auto k = dslash5_kernel<P, HOP, DAG, PRO, STAGE, CGU>;
+  auto k = dslash5_kernel<P, HOP, DAG, PRO, STAGE, CGU, SPLIT>;
   if (smem > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
@@ -818,6 +829,11 @@ static hipError_t launch_s(const DslashArgs& A, bool dag, bool pro, int threads,
 template <int P>
 static hipError_t launch_p(const DslashArgs& A, bool hop, bool dag, bool pro, int threads, size_t smem, int grid,
                            hipStream_t st) {
+  if (A.split_mask != 0) {
+    // the split interior exists for the plain staged hop only
+    if (!hop || dag || pro || !A.stage || A.cg_update) return hipErrorInvalidValue;
+    return launch_t<P, true, false, false, true, false, true>(A, threads, smem, grid, st);
+  }
   if (!hop) return A.cg_update ? hipErrorInvalidValue : launch_t<P, false, false, false, false>(A, threads, smem, grid, st);
   if (A.stage) return launch_s<P, true>(A, dag, pro, threads, smem, grid, st);
   return launch_s<P, false>(A, dag, pro, threads, smem, grid, st);
@@ -865,6 +881,187 @@ hipError_t dslash_launch(DslashArgs A, int prec, bool hop, bool dag, bool pro, i
     case I16: return launch_p<I16>(A, hop, dag, pro, threads, smem, grid, st);
   }
   return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Domain decomposition on one GPU: face packing and the exterior update.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int dd_extent(const Geom& g, int d) {
+  return d == 0 ? g.Lx : d == 1 ? g.Ly : d == 2 ? g.Lz : g.Lt;
+}
+
+// Face index of site X on the face orthogonal to mu: the lexicographic index
+// of the other three coordinates (x, y, z, t order, the first fastest), / 2.
+__device__ __forceinline__ int dd_face_index(const Geom& g, int mu, const int X[4]) {
+  int idx = 0;
+#pragma unroll
+  for (int d = 3; d >= 0; --d)
+    if (d != mu) idx = idx * dd_extent(g, d) + X[d];
+  return idx >> 1;
+}
+
+// The site of parity par with X[mu] = xm and face index f.  The fastest of
+// the other coordinates has an even extent (checked on the host), so 2f and
+// 2f + 1 differ only in it and one of the two has the right parity.
+__device__ __forceinline__ void dd_face_site(const Geom& g, int mu, int xm, int par, int f, int X[4]) {
+  int r = 2 * f;
+  int first = -1, sum = xm;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    if (d == mu) continue;
+    const int L = dd_extent(g, d);
+    X[d] = r % L;
+    r /= L;
+    if (first < 0) first = d;
+    else sum += X[d];
+  }
+  X[first] += (sum + par + X[first]) & 1;
+  X[mu] = xm;
+}
+
+template <int SIG, class R>
+__device__ __forceinline__ void project_mu(int mu, const Cplx<R> p[4][3], Cplx<R> h[2][3]) {
+  switch (mu) {
+    case 0: project<0, SIG>(p, h); break;
+    case 1: project<1, SIG>(p, h); break;
+    case 2: project<2, SIG>(p, h); break;
+    default: project<3, SIG>(p, h); break;
+  }
+}
+template <int SIG, class R>
+__device__ __forceinline__ void accumulate_mu(int mu, Cplx<R> acc[4][3], const Cplx<R> w[2][3]) {
+  switch (mu) {
+    case 0: accumulate<0, SIG>(acc, w); break;
+    case 1: accumulate<1, SIG>(acc, w); break;
+    case 2: accumulate<2, SIG>(acc, w); break;
+    default: accumulate<3, SIG>(acc, w); break;
+  }
+}
+
+// One thread per (face site, slice) of face kind blockIdx.y, RHS blockIdx.z.
+// The projectors are those of the plain hop H: (1 - g_mu) forward,
+// (1 + g_mu) backward.
+template <int P>
+__global__ __launch_bounds__(256) void k_dd_pack(DDArgs A) {
+  using R = typename PrecTraits<P>::Real;
+  const int kind = blockIdx.y, mu = kind >> 1, fb = kind & 1, slot = blockIdx.z;
+  if (!((A.split_mask >> mu) & 1)) return;
+  const int n = A.face_n[mu];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * A.g.L5) return;
+  const int f = t % n, s = t / n;
+  const int par = 1 - A.out_par;
+  int X[4];
+  dd_face_site(A.g, mu, fb == 0 ? 0 : dd_extent(A.g, mu) - 1, par, f, X);
+  const int cb = cb_index(A.g, X[0], X[1], X[2], X[3]);
+  R v[24];
+  SpinorIO<P>::load(A.in[slot], FieldDesc{A.g.Vh, A.g.L5}, cb, s, v);
+  Cplx<R> psi[4][3], h[2][3];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = {v[2 * k], v[2 * k + 1]};
+  if (fb == 0) {
+    project_mu<-1>(mu, psi, h);
+  } else {
+    Cplx<R> p2[2][3], U[3][3];
+    project_mu<+1>(mu, psi, p2);
+    LinkIO<P>::load(A.gauge, A.g.Vh, par, mu, cb, U);
+    colour_mul<true>(U, p2, h);
+  }
+  R* dst = reinterpret_cast<R*>(A.send[slot] + A.face_off[kind]) + (size_t)s * 12 * n + f;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    dst[(size_t)(2 * k) * n] = h[k / 3][k % 3].re;
+    dst[(size_t)(2 * k + 1) * n] = h[k / 3][k % 3].im;
+  }
+}
+
+// One thread per (output site, slice), RHS blockIdx.y: adds the hops across
+// split boundaries from the received faces (the forward ones multiplied by
+// the site's own link here, the antiperiodic sign applied at the t boundary).
+template <int P>
+__global__ __launch_bounds__(256) void k_dd_exterior(DDArgs A) {
+  using R = typename PrecTraits<P>::Real;
+  const int slot = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const Geom& g = A.g;
+  if (t >= g.Vh * g.L5) return;
+  const int cb = t % g.Vh, s = t / g.Vh;
+  int X[4];
+  site_coords(g, A.out_par, cb, X[0], X[1], X[2], X[3]);
+  Cplx<R> acc[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) acc[a][b] = {0, 0};
+  bool any = false;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (!((A.split_mask >> mu) & 1)) continue;
+    const int L = dd_extent(g, mu), n = A.face_n[mu];
+    for (int fb = 0; fb < 2; ++fb) {
+      if (fb == 0 ? X[mu] != L - 1 : X[mu] != 0) continue;
+      const R* src = reinterpret_cast<const R*>(A.recv[slot] + A.face_off[2 * mu + fb]) + (size_t)s * 12 * n +
+                     dd_face_index(g, mu, X);
+      Cplx<R> h[2][3], w[2][3];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) h[k / 3][k % 3] = {src[(size_t)(2 * k) * n], src[(size_t)(2 * k + 1) * n]};
+      if (fb == 0) {
+        Cplx<R> U[3][3];
+        LinkIO<P>::load(A.gauge, g.Vh, A.out_par, mu, cb, U);
+        colour_mul<false>(U, h, w);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) w[k / 3][k % 3] = h[k / 3][k % 3];
+      }
+      if (mu == 3 && g.tap) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) w[k / 3][k % 3] = {-w[k / 3][k % 3].re, -w[k / 3][k % 3].im};
+      }
+      if (fb == 0) accumulate_mu<-1>(mu, acc, w);
+      else accumulate_mu<+1>(mu, acc, w);
+      any = true;
+    }
+  }
+  if (!any) return;
+  const FieldDesc fd{g.Vh, g.L5};
+  R v[24];
+  SpinorIO<P>::load(A.out[slot], fd, cb, s, v);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    v[2 * k] += acc[k / 3][k % 3].re;
+    v[2 * k + 1] += acc[k / 3][k % 3].im;
+  }
+  SpinorIO<P>::store(A.out[slot], fd, cb, s, v);
+}
+
+hipError_t dd_pack(const DDArgs& A, int prec, hipStream_t st) {
+  int nmax = 0;
+  for (int mu = 0; mu < 4; ++mu)
+    if ((A.split_mask >> mu) & 1) nmax = std::max(nmax, A.face_n[mu]);
+  if (nmax == 0 || A.nslots < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(((size_t)nmax * A.g.L5 + 255) / 256), 8, (unsigned)A.nslots), blk(256);
+  switch (prec) {
+    case F64: launch_k(k_dd_pack<F64>, grid, blk, 0, st, A); break;
+    case F32: launch_k(k_dd_pack<F32>, grid, blk, 0, st, A); break;
+    case F16: launch_k(k_dd_pack<F16>, grid, blk, 0, st, A); break;
+    case BF16: launch_k(k_dd_pack<BF16>, grid, blk, 0, st, A); break;
+    case I16: launch_k(k_dd_pack<I16>, grid, blk, 0, st, A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t dd_exterior(const DDArgs& A, int prec, hipStream_t st) {
+  if (A.nslots < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(((size_t)A.g.Vh * A.g.L5 + 255) / 256), (unsigned)A.nslots), blk(256);
+  switch (prec) {
+    case F64: launch_k(k_dd_exterior<F64>, grid, blk, 0, st, A); break;
+    case F32: launch_k(k_dd_exterior<F32>, grid, blk, 0, st, A); break;
+    case F16: launch_k(k_dd_exterior<F16>, grid, blk, 0, st, A); break;
+    case BF16: launch_k(k_dd_exterior<BF16>, grid, blk, 0, st, A); break;
+    case I16: launch_k(k_dd_exterior<I16>, grid, blk, 0, st, A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace mdwf

@@ -34,6 +34,7 @@ struct Prog {
   int c1, c2, aux, reduce;
   double coef;
   int out_par;
+  int split = 0;  // split_mask of the domain-decomposed interior hop
 };
 
 }  // namespace mdwf

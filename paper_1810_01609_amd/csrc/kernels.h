@@ -74,6 +74,7 @@ struct DslashArgs {
   int order_bt;            // > 0: blocked (z, t) plane traversal with Bt time slices per block
   int order_yb;            // with order_bt > 0: the xy-plane is cut into order_yb bands of Ly/order_yb rows
   int nt_store;            // 1: the launch's field stores are streaming (non-temporal)
+  int split_mask;          // bit mu: hops across the mu boundary come from halo buffers (skipped here)
   int c1, c2, aux_mode, reduce;
   double coef_y;
   // CG update fused into the epilogue (cg_update = 1): with q the combined
@@ -87,6 +88,33 @@ struct DslashArgs {
 };
 
 hipError_t dslash_launch(DslashArgs A, int prec, bool hop, bool dag, bool pro, int cb_log2, hipStream_t st);
+
+// ---- domain decomposition, rehearsed on one GPU ---------------------------
+// A rank owning a block of the lattice computes the hop in three steps: pack
+// the faces its neighbours need (spin-projected half spinors, the backward
+// ones already multiplied by U^dag), the interior hop with every hop across a
+// split boundary left out (dslash5_kernel with split_mask), and the exterior
+// update adding the received faces.  Face kind k = 2 mu + fb: fb = 0 holds
+// (1 - g_mu) psi of the sites with x_mu = 0 (needed by the neighbour below as
+// its forward term), fb = 1 holds U_mu^dag (1 + g_mu) psi of the sites with
+// x_mu = L_mu - 1.  Layout per kind: [s][12 reals][face site], face sites of
+// one parity indexed by the lexicographic index of the other three
+// coordinates divided by two.
+struct DDArgs {
+  Geom g;
+  int out_par;           // parity of the hop's output sites
+  int split_mask;
+  const char* gauge;
+  char* const* in;       // [nslots] input half-fields (parity 1 - out_par)
+  char* const* out;      // [nslots] output half-fields (updated in place by the exterior step)
+  char* const* send;     // [nslots] packed faces
+  char* const* recv;     // [nslots] faces received from the neighbours
+  int nslots;
+  size_t face_off[8];    // byte offset of face kind k inside a slot's buffer
+  int face_n[4];         // sites of one parity on a face orthogonal to mu
+};
+hipError_t dd_pack(const DDArgs& A, int prec, hipStream_t st);
+hipError_t dd_exterior(const DDArgs& A, int prec, hipStream_t st);
 size_t dslash_lds_bytes(const DslashArgs& A, int prec, int cb_log2, bool hop);
 int dslash_max_threads(int prec);
 

@@ -179,3 +179,115 @@ extern "C" mdwf_status mdwf_dslash(mdwf_ctx* c, const mdwf_gauge* g, const mdwf_
   }
   return hip_err(c, e, "mdwf_dslash");
 }
+
+// The hop H_eo computed the way one rank of a domain-decomposed run computes
+// it, with the lattice as its own neighbour in every split dimension: pack the
+// faces, run the interior hop without the hops across split boundaries, and
+// add those from the faces.  The faces are read back from the packing buffer
+// itself (the exchange between ranks is the one step one GPU cannot show).
+extern "C" mdwf_status mdwf_hop_split(mdwf_ctx* c, const mdwf_gauge* g, const mdwf_action* act, int32_t prec,
+                                      int32_t split_mask, int32_t nrhs, const void* in, void* out,
+                                      double* phase_ms) {
+  if (c == nullptr) return MDWF_EINVAL;
+  std::string msg;
+  if (check_action_msg(act, msg) != MDWF_OK) return set_err(c, MDWF_EINVAL, "mdwf_hop_split: %s", msg.c_str());
+  if (split_mask < 0 || split_mask > 15) return set_err(c, MDWF_EINVAL, "mdwf_hop_split: split_mask must be in [0, 15]");
+  for (int m = 0; m < 4; ++m)
+    if (((split_mask >> m) & 1) && act->L[m] % 2 != 0)
+      return set_err(c, MDWF_EINVAL, "mdwf_hop_split: a split dimension needs an even extent");
+  if ((split_mask & 1) && act->L[1] % 2 != 0)
+    return set_err(c, MDWF_EINVAL, "mdwf_hop_split: splitting x needs an even Ly (face indexing)");
+  if (g == nullptr || in == nullptr || out == nullptr) return set_err(c, MDWF_EINVAL, "mdwf_hop_split: NULL argument");
+  for (int m = 0; m < 4; ++m)
+    if (g->L[m] != act->L[m]) return set_err(c, MDWF_EINVAL, "mdwf_hop_split: gauge lattice differs from the action's");
+  if (prec < MDWF_F64 || prec > MDWF_I16) return set_err(c, MDWF_EINVAL, "mdwf_hop_split: bad precision");
+  if (g->data[prec] == nullptr)
+    return set_err(c, MDWF_EINVAL, "mdwf_hop_split: gauge field was not loaded in precision %d", prec);
+  if (nrhs < 1) return set_err(c, MDWF_EINVAL, "mdwf_hop_split: nrhs must be >= 1");
+  {
+    const char* e = getenv("MDWF_STAGE");
+    if (split_mask != 0 && e != nullptr && e[0] == '0')
+      return set_err(c, MDWF_EINVAL, "mdwf_hop_split: the split interior needs the staged stencil (MDWF_STAGE=0)");
+  }
+  const Geom geom = make_geom(act);
+  const size_t ub = (size_t)geom.Vh * 2 * geom.L5 * 12 * 16;
+  const char* ib = static_cast<const char*>(in);
+  char* ob = static_cast<char*>(out);
+  if (ib < ob + ub * nrhs && ob < ib + ub * nrhs) return set_err(c, MDWF_EINVAL, "mdwf_hop_split: in and out overlap");
+  (void)hipSetDevice(c->device);
+  reset_tables(c);
+  DDArgs D{};
+  D.g = geom;
+  D.out_par = 0;
+  D.split_mask = split_mask;
+  D.gauge = static_cast<const char*>(g->data[prec]);
+  D.nslots = nrhs;
+  const int Ls[4] = {geom.Lx, geom.Ly, geom.Lz, geom.Lt};
+  const size_t rb = prec == MDWF_F64 ? 8 : 4;
+  size_t hb = 0;  // face buffer bytes per RHS
+  for (int m = 0; m < 4; ++m) {
+    D.face_n[m] = (int)((size_t)geom.Vh * 2 / Ls[m] / 2);
+    for (int fb = 0; fb < 2; ++fb) {
+      D.face_off[2 * m + fb] = hb;
+      if ((split_mask >> m) & 1) hb += round_up((size_t)D.face_n[m] * geom.L5 * 12 * rb, 256);
+    }
+  }
+  const size_t fb = round_up(spinor_field_bytes(prec, geom.L5, geom.Vh), 256);
+  const size_t hb_r = round_up(hb, 256);
+  mdwf_status st = ensure(c, c->dws, (fb * 2 + hb_r) * nrhs);
+  if (st != MDWF_OK) return st;
+  const Coef5 coef = make_coef(act);
+  std::vector<Coef5> coefs(nrhs, coef);
+  const Coef5* coef_d = static_cast<const Coef5*>(upload_bytes(c, coefs.data(), coefs.size() * sizeof(Coef5)));
+  std::vector<const void*> uin(nrhs), uout(nrhs), io(nrhs), oe(nrhs), hal(nrhs), nul(nrhs, nullptr);
+  char* w = static_cast<char*>(c->dws.p);
+  for (int r = 0; r < nrhs; ++r) {
+    uin[r] = ib + ub * r;
+    uout[r] = ob + ub * r;
+    io[r] = w + (fb * 2 + hb_r) * r;
+    oe[r] = w + (fb * 2 + hb_r) * r + fb;
+    hal[r] = w + (fb * 2 + hb_r) * r + 2 * fb;
+  }
+  char* const* UIN = upload_table(c, uin);
+  char* const* UOUT = upload_table(c, uout);
+  char* const* IO = upload_table(c, io);
+  char* const* OE = upload_table(c, oe);
+  char* const* HAL = upload_table(c, hal);
+  char* const* NUL = upload_table(c, nul);
+  if (!coef_d || !UIN || !UOUT || !IO || !OE || !HAL || !NUL)
+    return set_err(c, MDWF_EHIP, "mdwf_hop_split: table upload failed");
+  D.in = IO;
+  D.out = OE;
+  D.send = HAL;
+  D.recv = HAL;  // every split neighbour is the lattice itself
+  const int cls = prec == MDWF_F64 ? MDWF_PROF_DSLASH_F64 : MDWF_PROF_DSLASH_INNER;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (phase_ms != nullptr)
+    for (auto& x : ev) (void)hipEventCreate(&x);
+  hipError_t e = layout_user_to_half(geom, UIN, IO, 1, prec, nrhs, c->stream);
+  if (e == hipSuccess && ev[0]) e = hipEventRecord(ev[0], c->stream);
+  if (e == hipSuccess && split_mask != 0) e = dd_pack(D, prec, c->stream);
+  if (e == hipSuccess && ev[1]) e = hipEventRecord(ev[1], c->stream);
+  if (e == hipSuccess) {
+    Prog p = prog_HOP(0, false);
+    p.split = split_mask;
+    e = run_prog(c, g, geom, prec, p, IO, nullptr, OE, coef_d, nrhs, nullptr, 0, nullptr, 0, cls, false);
+  }
+  if (e == hipSuccess && ev[2]) e = hipEventRecord(ev[2], c->stream);
+  if (e == hipSuccess && split_mask != 0) e = dd_exterior(D, prec, c->stream);
+  if (e == hipSuccess && ev[3]) e = hipEventRecord(ev[3], c->stream);
+  if (e == hipSuccess) {
+    e = layout_half_to_user(geom, OE, UOUT, 0, prec, nrhs, c->stream);
+    if (e == hipSuccess) e = layout_half_to_user(geom, NUL, UOUT, 1, prec, nrhs, c->stream);
+  }
+  if (phase_ms != nullptr) {
+    if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+    for (int k = 0; k < 3; ++k) {
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      phase_ms[k] = ms;
+    }
+    for (auto& x : ev) (void)hipEventDestroy(x);
+  }
+  return hip_err(c, e, "mdwf_hop_split");
+}

@@ -109,6 +109,7 @@ _SIGS = {
     "mdwf_propagator_4d": (_I, [_P, ctypes.POINTER(Action), _I, _P, _P]),
     "mdwf_current_source": (_I, [_P, ctypes.POINTER(Action), _I, _I, _P, _P]),
     "mdwf_dslash": (_I, [_P, _P, ctypes.POINTER(Action), _I, _I, _I, _P, _P]),
+    "mdwf_hop_split": (_I, [_P, _P, ctypes.POINTER(Action), _I, _I, _I, _P, _P, ctypes.POINTER(ctypes.c_double)]),
     "mdwf_solve": (_I, [_P, _P, ctypes.POINTER(Action), ctypes.POINTER(CGOpts), _I, _P, _P,
                         ctypes.POINTER(CGStats)]),
     "mdwf_job_footprint": (ctypes.c_size_t, [ctypes.POINTER(Action), ctypes.POINTER(CGOpts), _I]),
@@ -274,6 +275,19 @@ class Context:
         st = lib().mdwf_dslash(self._h, gauge.handle, ctypes.byref(act), int(op), p, int(nrhs),
                                _ptr(inp, nb, "in"), _ptr(out, nb, "out"))
         self._check(st, "mdwf_dslash")
+
+    def hop_split(self, gauge, act: Action, prec, split_mask: int, inp, out, nrhs: int = 1, timed: bool = False):
+        """out_e = H_eo in_o as one rank of a domain-decomposed run computes it
+        (pack faces, interior hop, exterior update; the lattice is its own
+        neighbour in each split dimension).  With timed=True returns the GPU
+        milliseconds of the three steps."""
+        p = PREC[prec] if isinstance(prec, str) else int(prec)
+        nb = 16 * _numel(act) * nrhs
+        ms = (ctypes.c_double * 3)() if timed else None
+        st = lib().mdwf_hop_split(self._h, gauge.handle, ctypes.byref(act), p, int(split_mask), int(nrhs),
+                                  _ptr(inp, nb, "in"), _ptr(out, nb, "out"), ms)
+        self._check(st, "mdwf_hop_split")
+        return list(ms) if timed else None
 
     # ---- solve ----
     def solve(self, gauge, act: Action, opts: CGOpts, eta, psi, nrhs: int = 1, raise_on_fail=True):
