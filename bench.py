@@ -350,7 +350,7 @@ def main():
     ap.add_argument("--tune-save", default=None, help="dslash-only: write the tuned launch table here")
     ap.add_argument("--delta", type=float, default=None,
                     help="reliable-update threshold: an update when |r| falls below delta x its maximum since the "
-                         "last (default by inner precision: 0.01 for f32, 0.1 for 16-bit)")
+                         "last (default by inner precision: 3e-4 for f32, 0.3 for bf16, 0.1 for f16 and i16)")
     ap.add_argument("--check-every", type=int, default=8, help="CG iterations between host polls of the solver state")
     ap.add_argument("--fh", action="store_true", help="Feynman-Hellmann propagator pairs instead of single solves")
     ap.add_argument("--split", action="store_true",

@@ -248,7 +248,7 @@ class GPUBackend:
         return self.M.Action.make(req.volume, req.L5, self.b5, self.c5, self.M5, req.mq)
 
     def opts(self):
-        return self.M.CGOpts.make(tol=self.tol, inner=self.inner, delta=0.1)
+        return self.M.CGOpts.make(tol=self.tol, inner=self.inner)
 
     def footprint(self, req):
         # job state + the user-layout source and solution tensors
