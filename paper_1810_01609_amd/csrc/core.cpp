@@ -302,33 +302,36 @@ void prof_chunk_commit(mdwf_ctx* c, const std::vector<double>& active_frac) {
 // ---------------------------------------------------------------------------
 static int default_stage();
 
-// Time slices per traversal block: the largest of 8, 4, 2 dividing Lt whose
-// (Bt + 2) xy-planes of one RHS fit comfortably in a 4 MB XCD L2 (MDWF_BT
-// overrides; 0 = linear order).
-static int traversal_bt(const Geom& g, int prec, int nslots) {
-  const char* e = getenv("MDWF_BT");
-  if (e != nullptr && e[0] != 0) return atoi(e);
-  const double plane_bytes = (double)g.Lxh * g.Ly * g.L5 * spinor_site_bytes(prec);
-  for (int bt : {8, 4, 2}) {
-    if (g.Lt % bt != 0) continue;
-    if ((bt + 2) * plane_bytes * (nslots > 4 ? 4 : nslots) <= 3.0e6) return bt;
+// The untuned traversal (MDWF_BT and MDWF_YB override; Bt = 0 is the linear
+// order, one band is the whole xy-plane).  Measured on three lattices:
+//  * fifth dimension up to 12 slices (a workgroup column of at most 192 5D
+//    sites): bands of 4 y-rows, Bt = 2.  16^3 x 32: +3 % on the whole solve;
+//    32^3 x 64: the stencil 10 % (FP32) / 3 % (FP16) faster for one
+//    right-hand side, 24 % / 9 % for 12 fused ones; 1-, 2- and 8-row bands
+//    gained less;
+//  * longer columns (24^3 x 64, L5 = 16): 4-row bands were 2-3 % slower; whole
+//    planes with the largest Bt of 8, 4, 2 whose (Bt + 2) planes of one RHS
+//    fit in 3 MB of the XCD's 4 MB L2.
+static void traversal(const Geom& g, int prec, int nslots, int& bt, int& yb) {
+  const bool bands = g.L5 <= 12 && g.Ly % 4 == 0 && g.Ly / 4 > 1 && g.Lt % 2 == 0;
+  if (bands) {
+    bt = 2;
+    yb = g.Ly / 4;
+  } else {
+    yb = 1;
+    bt = g.Lt % 2 == 0 ? 2 : 0;
+    const double plane_bytes = (double)g.Lxh * g.Ly * g.L5 * spinor_site_bytes(prec);
+    for (int b : {8, 4}) {
+      if (g.Lt % b == 0 && (b + 2) * plane_bytes * (nslots > 4 ? 4 : nslots) <= 3.0e6) {
+        bt = b;
+        break;
+      }
+    }
   }
-  return g.Lt % 2 == 0 ? 2 : 0;
-}
-
-// y-bands of the blocked traversal (MDWF_YB overrides; 1 = whole xy-planes).
-// An xy-plane of 32 or more 16-site workgroups is cut into bands of 4 y-rows:
-// on the 32^3 x 64 lattice (L5 = 12) this cut the stencil's time by 10 % (FP32)
-// and 3 % (FP16) for one right-hand side and by 24 % and 9 % for 12 fused
-// ones; 2-row and 1-row bands (12 right-hand sides) and 8-row bands (one)
-// gained less.  On
-// 24^3 x 64 (18 workgroups per plane) no band width gained more than the noise.
-static int traversal_yb(const Geom& g, int prec, int nslots) {
-  (void)prec, (void)nslots;
-  const char* e = getenv("MDWF_YB");
-  if (e != nullptr && e[0] != 0) return atoi(e);
-  if (g.Lxh * g.Ly < 32 * 16 || g.Ly % 4 != 0) return 1;
-  return g.Ly / 4;
+  const char* e = getenv("MDWF_BT");
+  if (e != nullptr && e[0] != 0) bt = atoi(e);
+  e = getenv("MDWF_YB");
+  if (e != nullptr && e[0] != 0) yb = atoi(e);
 }
 
 // Streaming stores once the launch's output fields no longer fit the 256 MB
@@ -439,8 +442,7 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int pre
   A.aux_mode = pr.aux;
   A.reduce = pr.reduce;
   A.coef_y = pr.coef;
-  A.order_bt = traversal_bt(geom, prec, nslots);
-  A.order_yb = traversal_yb(geom, prec, nslots);
+  traversal(geom, prec, nslots, A.order_bt, A.order_yb);
   A.nt_store = streaming_stores(geom, prec, nslots);
   A.split_mask = pr.split;
   if (fuse != nullptr) {
