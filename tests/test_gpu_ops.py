@@ -175,6 +175,23 @@ def test_traversal_orders_bitwise(ctx, prec, monkeypatch):
     assert rel(outs[0], _oracle("NORMAL", U, x, oact)) < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "i16"])
+def test_streaming_stores_bitwise(ctx, prec, monkeypatch):
+    """Streaming (non-temporal) stores change where the written lines live in
+    the caches, never their values."""
+    from paper_1810_01609_amd import mdwf as M
+
+    U, act, oact, g = _setup(ctx, "banded")
+    x = S.random_spinor(act.lattice, act.L5, 410)
+    outs = []
+    for nt in ("0", "1"):
+        monkeypatch.setenv("MDWF_NT", nt)
+        out = empty_like_dev(x.shape)
+        ctx.dslash(g, act, M.OP_NORMAL, prec, to_dev(x), out)
+        outs.append(to_host(out))
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_gpu_identities(ctx):
     """Adjointness and gamma5-hermiticity measured on the GPU operators."""
     from paper_1810_01609_amd import mdwf as M
