@@ -72,6 +72,31 @@ def test_split_hop_matches(ctx, name, prec):
         assert rel(got, ref_h) < TOL_SAME[prec], (mask, rel(got, ref_h))
 
 
+def test_split_hop_benchmark_block(ctx):
+    """The block the benchmark times (one rank of c4 split 2x2x2 in y, z, t:
+    32x16x16x32, L5 = 12, y-band traversal): split against unsplit hop."""
+    import torch
+
+    from paper_1810_01609_amd import mdwf as M
+
+    c = S.CONFIGS["c4"]
+    L = (32, 16, 16, 32)
+    act = M.Action.make(L, c["L5"], c["b5"], c["c5"], c["M5"], c["mq"])
+    g = ctx.gauge_load(L, S.gauge_field(L, c["eps"], c["seed"]), precs=("f64", "f32", "f16"))
+    x = torch.zeros(act.spinor_shape(), dtype=torch.complex128, device="cuda")
+    ctx.source_z2(act, 7, 0, x)
+    ref = torch.zeros_like(x)
+    out = torch.zeros_like(x)
+    for prec in ("f64", "f32", "f16"):
+        log(f"[split] benchmark block {prec}")
+        ctx.dslash(g, act, M.OP_HOP_EO, prec, x, ref)
+        ctx.hop_split(g, act, prec, 0b1110, x, out)
+        err = float(torch.linalg.vector_norm(out - ref) / torch.linalg.vector_norm(ref))
+        assert err < TOL_SAME[prec], (prec, err)
+    del x, ref, out
+    g.free()
+
+
 def test_split_hop_multi_rhs_and_timing(ctx):
     from paper_1810_01609_amd import mdwf as M
 
