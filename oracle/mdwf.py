@@ -41,6 +41,8 @@ __all__ = [
     "gauge_transform_links", "gauge_transform_spinor",
     "dirac_at_sites", "vdot", "norm2",
     "gamma_product", "propagator_4d", "current_source", "fh_solve", "fh_operator",
+    "wall_inject_physical", "dminus", "physical_source", "current_source_physical", "fh_solve_physical",
+    "effective_propagator_4d",
 ]
 
 # ---------------------------------------------------------------------------
@@ -615,3 +617,72 @@ def fh_operator(psi, act, mask):
     insertion, so that D(lambda) = D + lambda J is the action with the
     current added; d/dlambda D(lambda)^{-1} eta = -D^{-1} J D^{-1} eta."""
     return current_source(propagator_4d(psi, act), act, mask)
+
+
+# ---------------------------------------------------------------------------
+# The physical 4D propagator of the Moebius action (Brower, Neff, Orginos,
+# arXiv:1206.5214; the paper's "Physics algorithms related" paragraph needs it
+# for the quark propagators its Feynman-Hellmann method combines).
+# Readings: the antiquark field sits on the opposite walls to the quark field
+# the read-out q = P- psi_0 + P+ psi_{L5-1} takes, so a 4D source xi enters
+# as eta_0 = P+ xi, eta_{L5-1} = P- xi; and the Moebius operator
+# D = (b5 D_W + 1) - (1 - c5 D_W) P5 is the Shamir-like operator
+# (1 - c5 D_W)^-1 (b5 D_W + 1) - P5 multiplied by the 4D factor
+# (1 - c5 D_W), which the source must carry: eta = (1 - c5 D_W) inject(xi).
+# Then q = S xi with S = (D_eff^-1 - 1) / (1 - mq), D_eff the truncated
+# overlap operator of the Moebius kernel (effective_propagator_4d).  With
+# c5 = 0 (Shamir) the factor is the identity.
+# ---------------------------------------------------------------------------
+def wall_inject_physical(xi, act):
+    """eta_0 = P+ xi, eta_{L5-1} = P- xi, zero elsewhere."""
+    eta = np.zeros(act.shape5, dtype=np.complex128)
+    eta[0] += _spin(PPLUS, xi)
+    eta[act.L5 - 1] += _spin(PMINUS, xi)
+    return eta
+
+
+def dminus(U, psi, act):
+    """(1 - c5 D_W) psi on every slice."""
+    return psi - act.c5 * dirac_wilson(U, psi, act)
+
+
+def physical_source(U, xi, act, mask=0):
+    """5D source of the physical 4D propagator: (1 - c5 D_W) inject(Gamma xi),
+    Gamma = gamma_product(mask) (mask 0: the identity)."""
+    return dminus(U, wall_inject_physical(_spin(gamma_product(mask), xi), act), act)
+
+
+def current_source_physical(U, q, act, mask):
+    """Sequential source of the physical Feynman-Hellmann propagator: the
+    current Gamma applied to the 4D propagator q at every site, entering as a
+    physical source."""
+    return physical_source(U, q, act, mask)
+
+
+def fh_solve_physical(U, xi, act, mask, tol=1e-12):
+    """(q, q_FH): the physical 4D propagator q = S xi and the sequential one
+    q_FH = S Gamma q, each read off the walls of a 5D solve."""
+    psi, _ = solve(U, physical_source(U, xi, act), act, tol=tol)
+    q = propagator_4d(psi, act)
+    psi2, _ = solve(U, current_source_physical(U, q, act, mask), act, tol=tol)
+    return q, propagator_4d(psi2, act)
+
+
+def effective_propagator_4d(U, act):
+    """Dense 4D matrix S = (D_eff^-1 - 1) / (1 - mq) on a tiny lattice, with
+    D_eff = (1 + mq)/2 + (1 - mq)/2 g5 eps(H_M), H_M = g5 (b5 + c5) D_W
+    (2 + (b5 - c5) D_W)^-1 (Hermitian) and eps(H) = [(1+H)^L5 - (1-H)^L5]
+    [(1+H)^L5 + (1-H)^L5]^-1, the polar approximation of sign(H) that L5
+    slices realise.  Rows and columns index [t][z][y][x][spin][col]."""
+    Lx, Ly, Lz, Lt = act.L
+    shape4 = (Lt, Lz, Ly, Lx, 4, 3)
+    n = int(np.prod(shape4))
+    Dw = dense_matrix(lambda v: dirac_wilson(U, v[None], act)[0], shape4)
+    g5 = np.kron(np.eye(n // 12), np.kron(GAMMA5, np.eye(3)))
+    I = np.eye(n)
+    HM = g5 @ ((act.b5 + act.c5) * Dw) @ np.linalg.inv(2.0 * I + (act.b5 - act.c5) * Dw)
+    A = np.linalg.matrix_power(I + HM, act.L5)
+    B = np.linalg.matrix_power(I - HM, act.L5)
+    E = (A - B) @ np.linalg.inv(A + B)
+    Deff = 0.5 * (1.0 + act.mq) * I + 0.5 * (1.0 - act.mq) * g5 @ E
+    return (np.linalg.inv(Deff) - I) / (1.0 - act.mq)

@@ -411,3 +411,71 @@ def test_feynman_hellmann_derivative(mask):
     assert _rel(-fd, psi_fh) < 1e-7
     got, _ = O.fh_solve(U, psi.reshape(shape), act, mask, tol=1e-13)
     assert _rel(got.ravel(), psi_fh) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# Physical 4D propagator of the Moebius action and the Feynman-Hellmann
+# sequential propagator built from it (P17-P18).
+# --------------------------------------------------------------------------
+def _dense_4d_propagator(U, act, source):
+    """Dense 4D map xi -> R D^-1 source(xi) through the 5D operator."""
+    Lx, Ly, Lz, Lt = act.L
+    shape4 = (Lt, Lz, Ly, Lx, 4, 3)
+    n4 = int(np.prod(shape4))
+    D5 = O.dense_matrix(lambda v: O.dirac(U, v, act), act.shape5)
+    B = np.zeros((D5.shape[0], n4), dtype=np.complex128)
+    e = np.zeros(n4, dtype=np.complex128)
+    for k in range(n4):
+        e[k] = 1.0
+        B[:, k] = source(e.reshape(shape4)).ravel()
+        e[k] = 0.0
+    X = np.linalg.solve(D5, B)
+    return np.stack([O.propagator_4d(X[:, k].reshape(act.shape5), act).ravel() for k in range(n4)], axis=1)
+
+
+@pytest.mark.parametrize("b5,c5", [(1.0, 0.0), (1.5, 0.5)])
+@pytest.mark.parametrize("L5", [1, 2, 4])
+def test_physical_propagator_is_truncated_overlap(b5, c5, L5):
+    """The 4D propagator read off the walls of D^-1 (1 - c5 D_W) inject(xi)
+    equals (D_eff^-1 - 1) / (1 - mq) xi, D_eff the truncated overlap operator
+    of the Moebius kernel H_M = g5 (b5 + c5) D_W / (2 + (b5 - c5) D_W),
+    built from dense 4D matrix functions with no 5D operator involved
+    (Shamir for c5 = 0, Moebius for c5 = 0.5; L5 = 1, 2, 4 on 2^3 x 4).
+    Without the (1 - c5 D_W) factor the Moebius case fails."""
+    act = O.Action((2, 2, 2, 4), L5, b5, c5, 1.3, 0.05)
+    U = S.gauge_field(act.L, 0.3, 3)
+    Sref = O.effective_propagator_4d(U, act)
+    Sg = _dense_4d_propagator(U, act, lambda xi: O.physical_source(U, xi, act))
+    assert _rel(Sg, Sref) < 1e-12, _rel(Sg, Sref)
+    if c5 != 0.0 and L5 > 1:
+        Sbare = _dense_4d_propagator(U, act, lambda xi: O.wall_inject_physical(xi, act))
+        assert _rel(Sbare, Sref) > 0.1
+
+
+def test_physical_source_shamir_limit_and_l5_one():
+    """c5 = 0: the physical source is the plain opposite-wall injection; L5 = 1:
+    both walls are slice 0 and the source is (1 - c5 D_W) xi."""
+    U = S.gauge_field((2, 2, 2, 4), 0.3, 4)
+    xi = S.random_spinor((2, 2, 2, 4), 1, 5)[0]
+    sh = O.Action((2, 2, 2, 4), 5, 1.0, 0.0, 1.3, 0.05)
+    assert np.array_equal(O.physical_source(U, xi, sh), O.wall_inject_physical(xi, sh))
+    one = O.Action((2, 2, 2, 4), 1, 1.5, 0.5, 1.3, 0.05)
+    want = xi - 0.5 * ((4.0 - 1.3) * xi - 0.5 * O.hop(U, xi[None], one)[0])
+    assert _rel(O.physical_source(U, xi, one)[0], want) < 1e-15
+
+
+@pytest.mark.parametrize("mask", [0, 11])
+def test_physical_feynman_hellmann_is_s_gamma_s(mask):
+    """The physical sequential propagator read off the second 5D solve equals
+    S Gamma S xi with S the dense 4D truncated-overlap propagator: the current
+    is inserted once, at every site, between two 4D propagators (the
+    Feynman-Hellmann derivative of the 4D propagator with Gamma added to the
+    4D action)."""
+    act = O.Action((2, 2, 2, 4), 4, 1.5, 0.5, 1.3, 0.05)
+    U = S.gauge_field(act.L, 0.3, 6)
+    Sref = O.effective_propagator_4d(U, act)
+    xi = S.random_spinor(act.L, 1, 8)[0]
+    q, qfh = O.fh_solve_physical(U, xi, act, mask, tol=1e-13)
+    G = np.kron(np.eye(xi.size // 12), np.kron(O.gamma_product(mask), np.eye(3)))
+    assert _rel(q.ravel(), Sref @ xi.ravel()) < 1e-10
+    assert _rel(qfh.ravel(), Sref @ (G @ (Sref @ xi.ravel()))) < 1e-10
