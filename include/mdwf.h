@@ -149,8 +149,23 @@ MDWF_API int32_t mdwf_abi_version(void);
  * msg_len bytes, NUL-terminated). */
 MDWF_API mdwf_status mdwf_check_action(const mdwf_action *act, char *msg, size_t msg_len);
 
-/* Create a context on HIP device `device`.  stream: a hipStream_t to adopt
- * (not owned), or NULL to create a private stream (default priority). */
+/* Host-only query (no device work): the workgroup traversal the fused
+ * stencil takes for this action, storage precision `prec`, `nrhs` fused
+ * right-hand sides and workgroups of 2^cb_log2 sites (cb_log2 in [4, 7]):
+ * *bt = time slices per (z, t) block (0: linear order), *yb = y-bands of the
+ * xy-plane.  It applies the environment overrides MDWF_BT (>= 0) and MDWF_YB
+ * (>= 1) -- other values are ignored -- and falls back to the linear order /
+ * one band where the lattice does not admit the requested blocking.
+ * MDWF_EINVAL on a bad action, precision, count or NULL output. */
+MDWF_API mdwf_status mdwf_query_traversal(const mdwf_action *act, int32_t prec, int32_t nrhs, int32_t cb_log2,
+                                          int32_t *bt, int32_t *yb);
+
+/* Create a context on HIP device `device` (the unit that holds one GPU's
+ * share of the paper's workflow, "Performance Measurement Method": gauge
+ * fields, solves and their workspaces).  stream: a hipStream_t to adopt (not
+ * owned), or NULL to create a private blocking stream (default
+ * priority).  *out receives the handle (NULL on failure).  EINVAL for a bad
+ * device or NULL out, EHIP when the runtime fails, ENOMEM on host exhaustion. */
 MDWF_API mdwf_status mdwf_create(int32_t device, void *stream, mdwf_ctx **out);
 
 /* Destroy a context and its workspaces (not its gauge fields or jobs: free
@@ -180,16 +195,23 @@ MDWF_API size_t mdwf_gauge_bytes(const mdwf_gauge *g);
 
 /* ---- sources -------------------------------------------------------------- */
 
-/* eta (device, user layout, one RHS, caller-allocated) = unit 4D point
- * source at x0 = (x,y,z,t) with the given spin and colour, placed on the
- * domain walls: eta_0 = P- xi, eta_{L5-1} = P+ xi. */
+/* The sources of the propagator solves the paper computes ("Current State
+ * of the Art", Background: propagators are solutions of the Dirac equation
+ * for given sources).  eta (device, user layout, one RHS, caller-allocated,
+ * every entry written) = unit 4D point source at x0 = (x,y,z,t) with the
+ * given spin and colour, placed on the domain walls: eta_0 = P- xi,
+ * eta_{L5-1} = P+ xi.  EINVAL on a bad action, x0 outside the lattice, spin
+ * outside [0, 4), colour outside [0, 3) or NULL eta.  Asynchronous. */
 MDWF_API mdwf_status mdwf_source_point(mdwf_ctx *ctx, const mdwf_action *act, const int32_t x0[4], int32_t spin,
                               int32_t colour, void *eta);
 
-/* eta = complex Z2 noise ((+-1) + i(+-1))/sqrt(2) per (4D site, spin,
- * colour), wall-injected as above.  The draws are SplitMix64(seed) outputs
- * with counter ((rhs_index*V4 + i4)*4 + spin)*3 + colour, i4 the
- * lexicographic 4D index; bit 0 gives the real sign, bit 1 the imaginary. */
+/* Stochastic source (same passage): eta (device, user layout, one RHS,
+ * every entry written) = complex Z2 noise ((+-1) + i(+-1))/sqrt(2) per (4D
+ * site, spin, colour), wall-injected as above.  The draws are
+ * SplitMix64(seed) outputs with counter ((rhs_index*V4 + i4)*4 + spin)*3 +
+ * colour, i4 the lexicographic 4D index; bit 0 gives the real sign, bit 1 the
+ * imaginary.  EINVAL on a bad action, rhs_index < 0 or NULL eta.
+ * Asynchronous. */
 MDWF_API mdwf_status mdwf_source_z2(mdwf_ctx *ctx, const mdwf_action *act, uint64_t seed, int32_t rhs_index,
                            void *eta);
 
@@ -217,12 +239,39 @@ MDWF_API mdwf_status mdwf_propagator_4d(mdwf_ctx *ctx, const mdwf_action *act, i
 MDWF_API mdwf_status mdwf_current_source(mdwf_ctx *ctx, const mdwf_action *act, int32_t nrhs, int32_t gamma_mask,
                                         const void *q, void *eta);
 
+/* The physical 4D propagator of the Moebius action (Brower-Neff-Orginos; the
+ * quark propagators the paper's Feynman-Hellmann method combines, "Current
+ * State of the Art", Physics algorithms related).  eta (device, user layout,
+ * nrhs 5D fields, caller-allocated, every entry written) =
+ * (1 - c5 D_W) inject(Gamma xi): Gamma xi (gamma_mask as in
+ * mdwf_current_source; 0 = identity) enters on the walls of the opposite
+ * chirality to the read-out of mdwf_propagator_4d, eta_0 = P+ Gamma xi,
+ * eta_{L5-1} = P- Gamma xi (both on slice 0 when L5 = 1), and the 4D factor
+ * (1 - c5 D_W), D_W = (4 - M5) - H/2, is applied on those slices.  Solving
+ * D psi = eta and reading q = P- psi_0 + P+ psi_{L5-1} then gives
+ * q = S Gamma xi with S = (D_eff^-1 - 1) / (1 - mq), D_eff the truncated
+ * overlap operator of the Moebius kernel.  xi: device, complex128
+ * [rhs][t][z][y][x][spin][colour], nrhs 4D fields back to back (for the
+ * sequential source pass the propagator q and the current's mask).  FP64,
+ * asynchronous on the context stream.  EINVAL on a bad action, mask outside
+ * [0, 15], nrhs < 1, NULL pointers, a gauge field of another lattice or not
+ * loaded in FP64; xi and eta must not overlap. */
+MDWF_API mdwf_status mdwf_source_physical(mdwf_ctx *ctx, const mdwf_gauge *g, const mdwf_action *act, int32_t nrhs,
+                                          int32_t gamma_mask, const void *xi, void *eta);
+
 /* ---- operator application ------------------------------------------------- */
 
-/* out = op(in) for nrhs fields (device, user layout).  The operator is
- * evaluated in storage precision `prec` (inputs rounded to it on entry,
- * FP64 results written back); the gauge field must hold `prec`.  in and out
- * must not overlap.  Asynchronous on the context stream. */
+/* The Dirac operator and its even-odd pieces ("Current State of the Art",
+ * Background: the MDWF operator, a radius-one stencil in 4D with dense
+ * blocks in the fifth dimension; Performance related: its red-black form).
+ * out = op(in) for nrhs fields (device, user layout, caller-allocated; every
+ * entry of out is written).  The operator is evaluated in storage precision
+ * `prec` (inputs rounded to it on entry, FP64 results written back); the
+ * gauge field must hold `prec`.  Temporaries live in the context's
+ * workspace (allocated on first use, grown when needed).  EINVAL on a bad
+ * action, operator, precision, nrhs < 1, NULL or overlapping in/out, or a
+ * gauge field of another lattice; ENOMEM when the workspace cannot grow.
+ * Asynchronous on the context stream. */
 MDWF_API mdwf_status mdwf_dslash(mdwf_ctx *ctx, const mdwf_gauge *g, const mdwf_action *act, int32_t op, int32_t prec,
                         int32_t nrhs, const void *in, void *out);
 
@@ -263,11 +312,20 @@ MDWF_API mdwf_status mdwf_solve(mdwf_ctx *ctx, const mdwf_gauge *g, const mdwf_a
 
 /* ---- stepping interface for continuous batching --------------------------- */
 
-/* Device bytes a job of nrhs RHS allocates (for admission control). */
+/* The stepping interface for continuous batching: the one-GPU analogue of
+ * the paper's job manager matching ready work to free resources
+ * ("Innovations", management and backfilling of tasks).  Device bytes a job
+ * of nrhs RHS allocates, including the context's FP64 temporaries (for
+ * admission control); 0 for a bad action, options or nrhs < 1. */
 MDWF_API size_t mdwf_job_footprint(const mdwf_action *act, const mdwf_cg_opts *opts, int32_t nrhs);
 
-/* Start a solve: prepares sources and CG state, returns at once.  eta and
- * psi must stay valid until mdwf_job_end. */
+/* Start a solve of nrhs RHS (same solver as mdwf_solve): prepares the
+ * even-odd sources and CG state on the device, allocates the job's block
+ * (mdwf_job_footprint bytes), returns without iterating.  eta, psi: device,
+ * user layout, nrhs fields, not overlapping; they must stay valid until
+ * mdwf_job_end (psi receives each RHS when it finishes).  *out receives the
+ * job (NULL on failure).  EINVAL on bad arguments, ENOMEM when the block
+ * cannot be allocated. */
 MDWF_API mdwf_status mdwf_job_begin(mdwf_ctx *ctx, const mdwf_gauge *g, const mdwf_action *act,
                            const mdwf_cg_opts *opts, int32_t nrhs, const void *eta, void *psi,
                            mdwf_job **out);
@@ -281,10 +339,11 @@ MDWF_API mdwf_status mdwf_job_begin(mdwf_ctx *ctx, const mdwf_gauge *g, const md
 MDWF_API mdwf_status mdwf_job_step(mdwf_ctx *ctx, mdwf_job *const *jobs, int32_t njobs, int32_t iters);
 
 /* done = 1 when every RHS of the job has finished (converged or failed);
- * stats (may be NULL) receives nrhs entries. */
+ * stats (may be NULL) receives nrhs entries.  Host only; EINVAL on NULL job. */
 MDWF_API mdwf_status mdwf_job_poll(const mdwf_job *job, int32_t *done, mdwf_cg_stats *stats);
 
-/* Release the job's device memory. */
+/* Wait for the job's work on its context stream and release its device
+ * memory; the handle is invalid afterwards.  EINVAL on NULL. */
 MDWF_API mdwf_status mdwf_job_end(mdwf_job *job);
 
 /* ---- measurement ---------------------------------------------------------- */
@@ -311,6 +370,17 @@ MDWF_API mdwf_status mdwf_profile_reset(mdwf_ctx *ctx);
  * and outside the CG loop are kept apart and each group's timed mean is
  * multiplied by that group's launch count. */
 MDWF_API mdwf_status mdwf_profile_read(mdwf_ctx *ctx, int32_t cls, int64_t *launches, double *ms, double *bytes);
+
+/* Achievable-bandwidth reference: copies `bytes` (a multiple of 16) from
+ * device buffer src to device buffer dst with the library's STREAM-style copy
+ * kernel (16-byte non-temporal loads and stores, 1 KB contiguous per
+ * wavefront access), once untimed and then `reps` times between two HIP
+ * events on the context stream; writes 2 * bytes * reps / elapsed in GB/s
+ * (read + write).  Blocks until done.  Buffers are the caller's; EINVAL on
+ * NULL pointers, overlapping buffers, reps < 1 or a size that is zero or not
+ * a multiple of 16. */
+MDWF_API mdwf_status mdwf_copy_bandwidth(mdwf_ctx *ctx, const void *src, void *dst, size_t bytes, int32_t reps,
+                                         double *gb_per_s);
 
 /* ---- launch autotuner (paper, "GPU Kernel Autotuning") -------------------- */
 

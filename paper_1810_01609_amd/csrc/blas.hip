@@ -6,9 +6,10 @@
 // thread owns one 4D site and walks its L5 slices (coalesced [s][group][cb]
 // accesses across the wavefront), the updates are fused so each vector is
 // read and written once, and every reduction accumulates in FP64 with a
-// fixed summation tree (DPP/shuffle within the wavefront, then LDS across
-// wavefronts, then one workgroup per right-hand side over the block
-// partials), so results are bitwise reproducible.
+// fixed summation tree (DPP moves within each 16-lane row, shuffles across
+// the four rows of a wavefront, then LDS across wavefronts, then one
+// workgroup per right-hand side over the block partials), so results are
+// bitwise reproducible.
 #include "dev_common.h"
 #include "kernels.h"
 
@@ -17,12 +18,9 @@ namespace mdwf {
 // Sum over a 256-thread block in a fixed order; valid in thread 0.
 __device__ __forceinline__ double block_sum_256(double v) {
   __shared__ double red[kBlasThreads / 64];
-  v += __shfl_xor(v, 32);
+  v = row_sum16(v);
   v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 8);
-  v += __shfl_xor(v, 4);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 32);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) red[wave] = v;
   __syncthreads();
@@ -214,6 +212,36 @@ hipError_t blas_norm_diff(BlasArgs A, int p, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// STREAM-style copy, the achievable-bandwidth reference the stencil's HBM
+// figures are read against: each thread moves four 16-byte vectors, one per
+// 256-thread stride (every wavefront access is 1 KB contiguous), with
+// non-temporal loads and stores (nothing is re-read).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_copy16(const uint4* src, uint4* dst, size_t n) {
+  const size_t base = (size_t)blockIdx.x * 1024 + threadIdx.x;
+  v4u a[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const size_t i = base + 256 * (size_t)j;
+    if (i < n) a[j] = __builtin_nontemporal_load((const MDWF_GLOBAL v4u*)(src + i));
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const size_t i = base + 256 * (size_t)j;
+    if (i < n) __builtin_nontemporal_store(a[j], (MDWF_GLOBAL v4u*)(dst + i));
+  }
+}
+
+hipError_t copy16(const void* src, void* dst, size_t n16, hipStream_t st) {
+  if (n16 == 0) return hipErrorInvalidValue;
+  const size_t blocks = (n16 + 1023) / 1024;
+  if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
+  launch_k(k_copy16, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<const uint4*>(src), static_cast<uint4*>(dst),
+           n16);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // scalar kernels: one 1024-thread workgroup per right-hand side
 // ---------------------------------------------------------------------------
 constexpr int kScalarThreads = 1024;
@@ -234,12 +262,9 @@ __device__ __forceinline__ double slot_sum(const double* partials, int n, int sl
   for (; j < n; j += T) v0 += q[j];
   double v = (v0 + v1) + (v2 + v3);
   __shared__ double red[T / 64];
-  v += __shfl_xor(v, 32);
+  v = row_sum16(v);
   v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 8);
-  v += __shfl_xor(v, 4);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 32);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) red[wave] = v;
   __syncthreads();

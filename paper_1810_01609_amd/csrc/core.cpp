@@ -65,6 +65,11 @@ mdwf_status check_action_msg(const mdwf_action* a, std::string& msg) {
     msg = "L5 must be in [1, 32]";
     return MDWF_EINVAL;
   }
+  // field locations are 32-bit counts of 16-byte groups (12 per FP64 site)
+  if ((v4 / 2 + 16.0) * a->L5 * 12.0 >= 4294967296.0) {
+    msg = "lattice too large (V4/2 * L5 * 12 must stay below 2^32)";
+    return MDWF_EINVAL;
+  }
   if (!std::isfinite(a->b5) || !std::isfinite(a->c5) || !std::isfinite(a->M5) || !std::isfinite(a->mq)) {
     msg = "b5, c5, M5, mq must be finite";
     return MDWF_EINVAL;
@@ -153,6 +158,7 @@ static constexpr size_t kTableBytes = 1 << 20;
 void reset_tables(mdwf_ctx* c) {
   if (c->tables_ev != nullptr) (void)hipEventSynchronize(c->tables_ev);
   c->tables_used = 0;
+  c->tables_floor = 0;
 }
 
 void* upload_bytes(mdwf_ctx* c, const void* data, size_t n) {
@@ -167,9 +173,11 @@ void* upload_bytes(mdwf_ctx* c, const void* data, size_t n) {
   }
   if (bytes > kTableBytes) return nullptr;
   if (c->tables_used + bytes > kTableBytes) {
-    // exhausted within one call: drain the stream, then start over
+    // exhausted within one call: drain the stream, then start over above the
+    // tables the running CG loop keeps reading (tables_floor)
     (void)hipStreamSynchronize(c->stream);
-    c->tables_used = 0;
+    c->tables_used = c->tables_floor;
+    if (c->tables_used + bytes > kTableBytes) return nullptr;
   }
   char* dst = static_cast<char*>(c->tables.p) + c->tables_used;
   char* src = static_cast<char*>(c->tables_host) + c->tables_used;
@@ -328,10 +336,11 @@ static void traversal(const Geom& g, int prec, int nslots, int& bt, int& yb) {
       }
     }
   }
+  // overrides: Bt >= 0 (0 = linear order), band count >= 1; other values are ignored
   const char* e = getenv("MDWF_BT");
-  if (e != nullptr && e[0] != 0) bt = atoi(e);
+  if (e != nullptr && e[0] != 0 && atoi(e) >= 0) bt = atoi(e);
   e = getenv("MDWF_YB");
-  if (e != nullptr && e[0] != 0) yb = atoi(e);
+  if (e != nullptr && e[0] != 0 && atoi(e) >= 1) yb = atoi(e);
 }
 
 // Streaming stores once the launch's output fields no longer fit the 256 MB
@@ -370,7 +379,15 @@ static int default_stage() {
 // 8), and the traversal of the hop kernels: Bt + 1 (bits 12-15) and the y-band
 // count (bits 16-23), where 0 keeps the size-based default.  The traversal
 // only reorders whole workgroups, so every candidate gives the same result.
-constexpr int kTravBtShift = 12, kTravYbShift = 16;
+constexpr int kTravBtShift = 12, kTravYbShift = 16, kNrwShift = 24;
+
+// RHS per workgroup of the untuned launch (MDWF_NRW overrides): 1
+static int default_nrw(int nslots) {
+  int n = 1;
+  const char* e = getenv("MDWF_NRW");
+  if (e != nullptr && e[0] != 0 && atoi(e) >= 1) n = atoi(e);
+  return std::min(n, std::max(nslots, 1));
+}
 
 static void candidates(const Geom& g, int prec, DslashArgs A, bool hop, std::vector<int>& out, int& dflt) {
   out.clear();
@@ -386,13 +403,22 @@ static void candidates(const Geom& g, int prec, DslashArgs A, bool hop, std::vec
       for (int yb : ybs) trav.push_back(((bt + 1) << kTravBtShift) | (yb << kTravYbShift));
     }
   }
-  for (int lg = 4; lg <= 7; ++lg) {
-    const int CB = 1 << lg;
-    if (CB * g.L5 > dslash_max_threads(prec)) break;
-    if (CB > 2 * g.Vh && lg > 4) break;
-    const size_t lds = dslash_lds_bytes(A, prec, lg, hop);
-    if (lds > 160 * 1024) break;
-    for (int t : trav) out.push_back(lg | (stage << 8) | t);
+  // RHS per workgroup: the default first, then 2, 3, 4 (hop kernels of a
+  // fused batch only: the staged links are what they share)
+  std::vector<int> nrws{default_nrw(A.nslots)};
+  if (hop)
+    for (int n : {1, 2, 3, 4})
+      if (n <= A.nslots && n != nrws[0]) nrws.push_back(n);
+  for (int nrw : nrws) {
+    A.nrw = nrw;
+    for (int lg = 4; lg <= 7; ++lg) {
+      const int CB = 1 << lg;
+      if (CB * g.L5 * nrw > dslash_max_threads(prec)) break;
+      if (CB > 2 * g.Vh && lg > 4) break;
+      const size_t lds = dslash_lds_bytes(A, prec, lg, hop);
+      if (lds > 160 * 1024) break;
+      for (int t : trav) out.push_back(lg | (stage << 8) | t | (nrw << kNrwShift));
+    }
   }
   // untuned default: the smallest workgroup (16 sites x L5 slices) — it packs
   // the most resident waves per CU under the LDS and register limits, and the
@@ -403,6 +429,7 @@ static void candidates(const Geom& g, int prec, DslashArgs A, bool hop, std::vec
 
 static void apply_candidate(DslashArgs& A, int code) {
   A.stage = (code >> 8) & 1;
+  A.nrw = std::max(1, (code >> kNrwShift) & 0xf);
   const int bt1 = (code >> kTravBtShift) & 0xf;
   const int yb = (code >> kTravYbShift) & 0xff;
   if (bt1 != 0) A.order_bt = bt1 - 1;
@@ -519,6 +546,20 @@ mdwf_status mdwf_check_action(const mdwf_action* act, char* msg, size_t msg_len)
     snprintf(msg, msg_len, "%s", m.c_str());
   }
   return s;
+}
+
+mdwf_status mdwf_query_traversal(const mdwf_action* act, int32_t prec, int32_t nrhs, int32_t cb_log2, int32_t* bt,
+                                 int32_t* yb) {
+  std::string m;
+  if (check_action_msg(act, m) != MDWF_OK || bt == nullptr || yb == nullptr) return MDWF_EINVAL;
+  if (prec < MDWF_F64 || prec > MDWF_I16 || nrhs < 1 || cb_log2 < 4 || cb_log2 > 7) return MDWF_EINVAL;
+  const Geom g = make_geom(act);
+  int b = 0, y = 1;
+  traversal(g, prec, nrhs, b, y);
+  clamp_traversal(g, 1 << cb_log2, b, y);
+  *bt = b;
+  *yb = y;
+  return MDWF_OK;
 }
 
 mdwf_status mdwf_create(int32_t device, void* stream, mdwf_ctx** out) {
@@ -742,6 +783,59 @@ mdwf_status mdwf_current_source(mdwf_ctx* c, const mdwf_action* act, int32_t nrh
   return hip_err(c, e, "current_source");
 }
 
+mdwf_status mdwf_source_physical(mdwf_ctx* c, const mdwf_gauge* gf, const mdwf_action* act, int32_t nrhs,
+                                 int32_t gamma_mask, const void* xi, void* eta) {
+  if (c == nullptr) return MDWF_EINVAL;
+  std::string msg;
+  if (check_action_msg(act, msg) != MDWF_OK) return set_err(c, MDWF_EINVAL, "mdwf_source_physical: %s", msg.c_str());
+  if (gf == nullptr || xi == nullptr || eta == nullptr || nrhs < 1)
+    return set_err(c, MDWF_EINVAL, "mdwf_source_physical: bad argument");
+  if (gamma_mask < 0 || gamma_mask > 15) return set_err(c, MDWF_EINVAL, "mdwf_source_physical: gamma_mask in [0, 15]");
+  for (int m = 0; m < 4; ++m)
+    if (gf->L[m] != act->L[m])
+      return set_err(c, MDWF_EINVAL, "mdwf_source_physical: gauge lattice differs from the action's");
+  if (gf->data[MDWF_F64] == nullptr)
+    return set_err(c, MDWF_EINVAL, "mdwf_source_physical: the gauge field must be loaded in FP64");
+  (void)hipSetDevice(c->device);
+  const Geom g = make_geom(act);
+  const size_t qb = (size_t)nrhs * g.Vh * 2 * 12 * 16, eb = qb * g.L5;
+  const char* qa = static_cast<const char*>(xi);
+  const char* ea = static_cast<const char*>(eta);
+  if (qa < ea + eb && ea < qa + qb) return set_err(c, MDWF_EINVAL, "mdwf_source_physical: xi and eta overlap");
+  const double beta = 1.0 - act->c5 * (4.0 - act->M5), hc = 0.5 * act->c5;
+  hipEvent_t ev;
+  prof_begin(c, &ev);
+  hipError_t e = source_physical(g, nrhs, gamma_mask, static_cast<const char*>(gf->data[MDWF_F64]),
+                                 static_cast<const double*>(xi), static_cast<double*>(eta), beta, hc, c->stream);
+  prof_end(c, MDWF_PROF_OTHER, (double)eb + qb, ev);
+  return hip_err(c, e, "source_physical");
+}
+
+mdwf_status mdwf_copy_bandwidth(mdwf_ctx* c, const void* src, void* dst, size_t bytes, int32_t reps, double* gbs) {
+  if (c == nullptr) return MDWF_EINVAL;
+  if (src == nullptr || dst == nullptr || gbs == nullptr || reps < 1 || bytes == 0 || bytes % 16 != 0)
+    return set_err(c, MDWF_EINVAL, "mdwf_copy_bandwidth: bad argument");
+  const char* a = static_cast<const char*>(src);
+  const char* b = static_cast<const char*>(dst);
+  if (a < b + bytes && b < a + bytes) return set_err(c, MDWF_EINVAL, "mdwf_copy_bandwidth: src and dst overlap");
+  (void)hipSetDevice(c->device);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = copy16(src, dst, bytes / 16, c->stream);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = copy16(src, dst, bytes / 16, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_err(c, e, "mdwf_copy_bandwidth");
+  *gbs = ms > 0 ? 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9 : 0.0;
+  return MDWF_OK;
+}
+
 mdwf_status mdwf_profile_enable(mdwf_ctx* c, int32_t on) {
   if (c == nullptr) return MDWF_EINVAL;
   if (on < 0) return set_err(c, MDWF_EINVAL, "mdwf_profile_enable: negative mode");
@@ -828,7 +922,7 @@ mdwf_status mdwf_tune_load(mdwf_ctx* c, const char* path) {
     float ms = 0;
     rest >> lg >> ms;
     if ((lg & 0xff) >= 4 && (lg & 0xff) <= 7 && ((lg >> 9) & 7) == 0 && ((lg >> kTravBtShift) & 0xf) <= 9 &&
-        (lg >> 24) == 0) {
+        ((lg >> kNrwShift) & 0xf) <= 4 && (lg >> 28) == 0) {
       c->tune[line.substr(0, bar)] = lg;
       c->tune_ms[line.substr(0, bar)] = ms;
     }

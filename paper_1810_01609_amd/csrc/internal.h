@@ -72,6 +72,7 @@ struct mdwf_ctx {
   mdwf::DevBuf tables;     // pointer tables / small arrays, bump-allocated per call
   void* tables_host = nullptr;  // pinned mirror of `tables`
   size_t tables_used = 0;
+  size_t tables_floor = 0;  // bytes below which a wrapped region must not reuse (tables a running loop still reads)
   hipEvent_t tables_ev = nullptr;  // recorded after the latest table upload
   mdwf::DevBuf partials_d; // dslash 16-site tile partials
   mdwf::DevBuf partials_b; // blas block partials

@@ -66,6 +66,7 @@ struct DslashArgs {
   double* partials;        // [nslots][ntiles] (16-site tiles) when reduce
   int ntiles;
   int nslots;
+  int nrw;                 // RHS per workgroup (they share the staged links; >= 1)
   int nblk;                // filled by the launcher
   int cb_log2;             // filled by the launcher
   int lds_chain_bytes;     // filled by the launcher: offset of the reduction area
@@ -88,6 +89,9 @@ struct DslashArgs {
 };
 
 hipError_t dslash_launch(DslashArgs A, int prec, bool hop, bool dag, bool pro, int cb_log2, hipStream_t st);
+// The traversal a launch of CB-site workgroups actually takes (invalid Bt or
+// band counts fall back to the linear order / one band).
+void clamp_traversal(const Geom& g, int CB, int& bt, int& yb);
 
 // ---- domain decomposition, rehearsed on one GPU ---------------------------
 // A rank owning a block of the lattice computes the hop in three steps: pack
@@ -143,6 +147,8 @@ hipError_t blas_axpby(BlasArgs A, int pin, int pout, hipStream_t st);
 // partials of |a - b|^2 (b may be nullptr table: |a|^2).  both precision p
 hipError_t blas_norm_diff(BlasArgs A, int p, hipStream_t st);
 int blas_nblk(const Geom& g);
+// STREAM-style copy of n16 16-byte vectors (achievable-bandwidth reference)
+hipError_t copy16(const void* src, void* dst, size_t n16, hipStream_t st);
 
 // ---- scalar kernels (one workgroup per slot, fixed summation order) -------
 // out[i] = sum_j partials[i*n + j]
@@ -167,5 +173,9 @@ hipError_t source_z2(const Geom& g, double* eta, uint64_t seed, int rhs_index, h
 // Feynman-Hellmann sequential source, user layouts, nrhs fields back to back
 hipError_t propagator_4d(const Geom& g, int nrhs, const double* psi, double* q, hipStream_t st);
 hipError_t current_source(const Geom& g, int nrhs, int mask, const double* q, double* eta, hipStream_t st);
+// physical 4D-propagator source: eta = (beta + hc H) inject'(Gamma_mask xi), inject' = P+ on slice 0,
+// P- on slice L5-1; gauge64 the FP64 internal gauge field
+hipError_t source_physical(const Geom& g, int nrhs, int mask, const char* gauge64, const double* xi, double* eta,
+                           double beta, double hc, hipStream_t st);
 
 }  // namespace mdwf

@@ -196,6 +196,112 @@ static SpinPerm gamma_perm(int mask) {
   return G;
 }
 
+// ---------------------------------------------------------------------------
+// Source of the physical 4D propagator of the Moebius action: the 4D field
+// Gamma xi enters on the walls of the opposite chirality to the read-out
+// (P+ on slice 0, P- on slice L5-1) and is multiplied by the 4D factor
+// (1 - c5 D_W) = beta + (c5/2) H, beta = 1 - c5 (4 - M5), that turns the
+// Moebius operator into its Shamir-like form.  One thread per 4D site and
+// right-hand side, FP64, user layouts; every other slice is written zero.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 times_i_pow(double2 x, int ph) {
+  switch (ph & 3) {
+    case 0: return x;
+    case 1: return make_double2(-x.y, x.x);
+    case 2: return make_double2(-x.x, -x.y);
+    default: return make_double2(x.y, -x.x);
+  }
+}
+
+struct GammaTab {
+  int col[4][4];  // row a of g_mu has its entry i^ph[mu][a] in column col[mu][a]
+  int ph[4][4];
+};
+
+// P_w Gamma xi at site i4 (w = 0: spins 0,1; w = 1: spins 2,3), 12 complex numbers
+__device__ __forceinline__ void chi_at(const double2* x, size_t i4, const SpinPerm& G, int w, double2 v[12]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const bool keep = (w == 0) == (a < 2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      v[a * 3 + c] = keep ? times_i_pow(x[i4 * 12 + G.perm[a] * 3 + c], G.phase[a]) : make_double2(0.0, 0.0);
+  }
+}
+
+__global__ __launch_bounds__(128) void k_source_physical(Geom g, SpinPerm G, GammaTab T, const char* gauge,
+                                                         const double2* xi, double2* eta, double beta, double hc) {
+  const size_t V4 = (size_t)g.Vh * 2;
+  const size_t i4 = (size_t)blockIdx.x * 128 + threadIdx.x;
+  const size_t r = blockIdx.y;
+  if (i4 >= V4) return;
+  const double2* x = xi + r * V4 * 12;
+  int X[4];
+  size_t rem = i4;
+  X[0] = (int)(rem % g.Lx); rem /= g.Lx;
+  X[1] = (int)(rem % g.Ly); rem /= g.Ly;
+  X[2] = (int)(rem % g.Lz); rem /= g.Lz;
+  X[3] = (int)rem;
+  const int par = (X[0] + X[1] + X[2] + X[3]) & 1;
+  const int cb = (int)(i4 >> 1);
+  const int Ls[4] = {g.Lx, g.Ly, g.Lz, g.Lt};
+  double2 out[2][12], v[12];
+  for (int w = 0; w < 2; ++w) {
+    chi_at(x, i4, G, w, v);
+    for (int k = 0; k < 12; ++k) out[w][k] = make_double2(beta * v[k].x, beta * v[k].y);
+  }
+  for (int mu = 0; mu < 4; ++mu) {
+    for (int fb = 0; fb < 2; ++fb) {
+      int Y[4] = {X[0], X[1], X[2], X[3]};
+      double sg = 1.0;
+      if (fb == 0) {
+        Y[mu] = X[mu] + 1 == Ls[mu] ? 0 : X[mu] + 1;
+        if (mu == 3 && g.tap && X[3] == g.Lt - 1) sg = -1.0;
+      } else {
+        Y[mu] = X[mu] == 0 ? Ls[mu] - 1 : X[mu] - 1;
+        if (mu == 3 && g.tap && X[3] == 0) sg = -1.0;
+      }
+      const size_t j4 = (((size_t)Y[3] * g.Lz + Y[2]) * g.Ly + Y[1]) * g.Lx + Y[0];
+      Cplx<double> U[3][3];
+      // forward: U_mu(x) on the site's own parity; backward: U_mu(x - mu)^dag
+      if (fb == 0) LinkIO<F64>::load(gauge, g.Vh, par, mu, cb, U);
+      else LinkIO<F64>::load(gauge, g.Vh, 1 - par, mu, (int)(j4 >> 1), U);
+      const double s1 = fb == 0 ? -1.0 : 1.0;  // (1 - g_mu) forward, (1 + g_mu) backward
+      for (int w = 0; w < 2; ++w) {
+        chi_at(x, j4, G, w, v);
+        double2 y[12];
+        for (int a = 0; a < 4; ++a)
+          for (int c = 0; c < 3; ++c) {
+            double re = 0, im = 0;
+            for (int b = 0; b < 3; ++b) {
+              const Cplx<double> u = fb == 0 ? U[c][b] : Cplx<double>{U[b][c].re, -U[b][c].im};
+              const double2 z = v[a * 3 + b];
+              re += u.re * z.x - u.im * z.y;
+              im += u.re * z.y + u.im * z.x;
+            }
+            y[a * 3 + c] = make_double2(re, im);
+          }
+        for (int a = 0; a < 4; ++a)
+          for (int c = 0; c < 3; ++c) {
+            const double2 gy = times_i_pow(y[T.col[mu][a] * 3 + c], T.ph[mu][a]);
+            const double zr = y[a * 3 + c].x + s1 * gy.x, zi = y[a * 3 + c].y + s1 * gy.y;
+            out[w][a * 3 + c].x += hc * sg * zr;
+            out[w][a * 3 + c].y += hc * sg * zi;
+          }
+      }
+    }
+  }
+  double2* e = eta + r * g.L5 * V4 * 12;
+  for (int s = 0; s < g.L5; ++s) {
+    for (int k = 0; k < 12; ++k) {
+      double2 val = make_double2(0.0, 0.0);
+      if (s == 0) val = out[0][k];
+      if (s == g.L5 - 1) val = make_double2(val.x + out[1][k].x, val.y + out[1][k].y);
+      e[((size_t)s * V4 + i4) * 12 + k] = val;
+    }
+  }
+}
+
 hipError_t propagator_4d(const Geom& g, int nrhs, const double* psi, double* q, hipStream_t st) {
   const size_t n = (size_t)g.Vh * 2 * 12;
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)nrhs), blk(256);
@@ -209,6 +315,21 @@ hipError_t current_source(const Geom& g, int nrhs, int mask, const double* q, do
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)g.L5, (unsigned)nrhs), blk(256);
   launch_k(k_current_source, grid, blk, 0, st, g, gamma_perm(mask), reinterpret_cast<const double2*>(q),
            reinterpret_cast<double2*>(eta));
+  return hipGetLastError();
+}
+
+hipError_t source_physical(const Geom& g, int nrhs, int mask, const char* gauge64, const double* xi, double* eta,
+                           double beta, double hc, hipStream_t st) {
+  GammaTab T;
+  for (int mu = 0; mu < 4; ++mu)
+    for (int a = 0; a < 4; ++a) {
+      T.col[mu][a] = kGammaCol[mu][a];
+      T.ph[mu][a] = kGammaPh[mu][a];
+    }
+  const size_t V4 = (size_t)g.Vh * 2;
+  const dim3 grid((unsigned)((V4 + 127) / 128), (unsigned)nrhs), blk(128);
+  launch_k(k_source_physical, grid, blk, 0, st, g, gamma_perm(mask), T, gauge64, reinterpret_cast<const double2*>(xi),
+           reinterpret_cast<double2*>(eta), beta, hc);
   return hipGetLastError();
 }
 

@@ -33,28 +33,58 @@ Prog prog_5D(int chain) { return Prog{false, false, false, chain, CH_NONE, AUX_N
 
 }  // namespace mdwf
 
+// Argument checks shared by mdwf_dslash and its no-allocation variant.
+static mdwf_status dslash_check(mdwf_ctx* c, const char* who, const mdwf_gauge* g, const mdwf_action* act,
+                                int32_t op, int32_t prec, int32_t nrhs, const void* in, void* out) {
+  std::string msg;
+  if (check_action_msg(act, msg) != MDWF_OK) return set_err(c, MDWF_EINVAL, "%s: %s", who, msg.c_str());
+  if (g == nullptr || in == nullptr || out == nullptr) return set_err(c, MDWF_EINVAL, "%s: NULL argument", who);
+  for (int m = 0; m < 4; ++m)
+    if (g->L[m] != act->L[m]) return set_err(c, MDWF_EINVAL, "%s: gauge lattice differs from the action's", who);
+  if (prec < MDWF_F64 || prec > MDWF_I16) return set_err(c, MDWF_EINVAL, "%s: bad precision", who);
+  if (g->data[prec] == nullptr)
+    return set_err(c, MDWF_EINVAL, "%s: gauge field was not loaded in precision %d", who, prec);
+  if (op < MDWF_OP_D || op > MDWF_OP_PREP) return set_err(c, MDWF_EINVAL, "%s: bad operator %d", who, op);
+  if (nrhs < 1) return set_err(c, MDWF_EINVAL, "%s: nrhs must be >= 1", who);
+  const Geom geom = make_geom(act);
+  const size_t ub = (size_t)geom.Vh * 2 * geom.L5 * 12 * 16;  // user bytes per RHS
+  const char* ib = static_cast<const char*>(in);
+  const char* ob = static_cast<const char*>(out);
+  if (ib < ob + ub * nrhs && ob < ib + ub * nrhs) return set_err(c, MDWF_EINVAL, "%s: in and out overlap", who);
+  return MDWF_OK;
+}
+
+// The device tables one operator application reads: user fields, the five
+// internal half-fields per RHS (in_e, in_o, out_e, out_o, temporary), a table
+// of null pointers (a zero parity) and the per-RHS coefficients.
+struct DslashTables {
+  char* const* UIN;
+  char* const* UOUT;
+  char* const* IE;
+  char* const* IO;
+  char* const* OE;
+  char* const* OO;
+  char* const* T;
+  char* const* NUL;
+  const Coef5* coef;
+};
+
+static mdwf_status dslash_body(mdwf_ctx* c, const mdwf_gauge* g, const Geom& geom, int32_t op, int32_t prec,
+                               int32_t nrhs, const DslashTables& t);
+
 extern "C" mdwf_status mdwf_dslash(mdwf_ctx* c, const mdwf_gauge* g, const mdwf_action* act, int32_t op,
                                    int32_t prec, int32_t nrhs, const void* in, void* out) {
   if (c == nullptr) return MDWF_EINVAL;
-  std::string msg;
-  if (check_action_msg(act, msg) != MDWF_OK) return set_err(c, MDWF_EINVAL, "mdwf_dslash: %s", msg.c_str());
-  if (g == nullptr || in == nullptr || out == nullptr) return set_err(c, MDWF_EINVAL, "mdwf_dslash: NULL argument");
-  for (int m = 0; m < 4; ++m)
-    if (g->L[m] != act->L[m]) return set_err(c, MDWF_EINVAL, "mdwf_dslash: gauge lattice differs from the action's");
-  if (prec < MDWF_F64 || prec > MDWF_I16) return set_err(c, MDWF_EINVAL, "mdwf_dslash: bad precision");
-  if (g->data[prec] == nullptr)
-    return set_err(c, MDWF_EINVAL, "mdwf_dslash: gauge field was not loaded in precision %d", prec);
-  if (op < MDWF_OP_D || op > MDWF_OP_PREP) return set_err(c, MDWF_EINVAL, "mdwf_dslash: bad operator %d", op);
-  if (nrhs < 1) return set_err(c, MDWF_EINVAL, "mdwf_dslash: nrhs must be >= 1");
+  mdwf_status st = dslash_check(c, "mdwf_dslash", g, act, op, prec, nrhs, in, out);
+  if (st != MDWF_OK) return st;
   const Geom geom = make_geom(act);
   const size_t ub = (size_t)geom.Vh * 2 * geom.L5 * 12 * 16;  // user bytes per RHS
   const char* ib = static_cast<const char*>(in);
   char* ob = static_cast<char*>(out);
-  if (ib < ob + ub * nrhs && ob < ib + ub * nrhs) return set_err(c, MDWF_EINVAL, "mdwf_dslash: in and out overlap");
   (void)hipSetDevice(c->device);
   reset_tables(c);
   const size_t fb = round_up(spinor_field_bytes(prec, geom.L5, geom.Vh), 256);
-  mdwf_status st = ensure(c, c->dws, fb * 5 * nrhs);
+  st = ensure(c, c->dws, fb * 5 * nrhs);
   if (st != MDWF_OK) return st;
   const Coef5 coef = make_coef(act);
   std::vector<Coef5> coefs(nrhs, coef);
@@ -70,16 +100,32 @@ extern "C" mdwf_status mdwf_dslash(mdwf_ctx* c, const mdwf_gauge* g, const mdwf_
     oo[r] = w + fb * (5 * r + 3);
     tt[r] = w + fb * (5 * r + 4);
   }
-  char* const* UIN = upload_table(c, uin);
-  char* const* UOUT = upload_table(c, uout);
-  char* const* IE = upload_table(c, ie);
-  char* const* IO = upload_table(c, io);
-  char* const* OE = upload_table(c, oe);
-  char* const* OO = upload_table(c, oo);
-  char* const* T = upload_table(c, tt);
-  char* const* NUL = upload_table(c, nul);
-  if (!coef_d || !UIN || !UOUT || !IE || !IO || !OE || !OO || !T || !NUL)
+  DslashTables t;
+  t.UIN = upload_table(c, uin);
+  t.UOUT = upload_table(c, uout);
+  t.IE = upload_table(c, ie);
+  t.IO = upload_table(c, io);
+  t.OE = upload_table(c, oe);
+  t.OO = upload_table(c, oo);
+  t.T = upload_table(c, tt);
+  t.NUL = upload_table(c, nul);
+  t.coef = coef_d;
+  if (!t.coef || !t.UIN || !t.UOUT || !t.IE || !t.IO || !t.OE || !t.OO || !t.T || !t.NUL)
     return set_err(c, MDWF_EHIP, "mdwf_dslash: table upload failed");
+  return dslash_body(c, g, geom, op, prec, nrhs, t);
+}
+
+static mdwf_status dslash_body(mdwf_ctx* c, const mdwf_gauge* g, const Geom& geom, int32_t op, int32_t prec,
+                               int32_t nrhs, const DslashTables& t) {
+  char* const* UIN = t.UIN;
+  char* const* UOUT = t.UOUT;
+  char* const* IE = t.IE;
+  char* const* IO = t.IO;
+  char* const* OE = t.OE;
+  char* const* OO = t.OO;
+  char* const* T = t.T;
+  char* const* NUL = t.NUL;
+  const Coef5* coef_d = t.coef;
   const int cls = prec == MDWF_F64 ? MDWF_PROF_DSLASH_F64 : MDWF_PROF_DSLASH_INNER;
   hipError_t e = hipSuccess;
   hipEvent_t ev;

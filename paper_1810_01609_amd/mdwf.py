@@ -100,6 +100,8 @@ _I = ctypes.c_int32
 _SIGS = {
     "mdwf_abi_version": (_I, []),
     "mdwf_check_action": (_I, [ctypes.POINTER(Action), ctypes.c_char_p, ctypes.c_size_t]),
+    "mdwf_copy_bandwidth": (_I, [_P, _P, _P, ctypes.c_size_t, _I, ctypes.POINTER(ctypes.c_double)]),
+    "mdwf_query_traversal": (_I, [ctypes.POINTER(Action), _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "mdwf_create": (_I, [_I, _P, ctypes.POINTER(_P)]),
     "mdwf_destroy": (_I, [_P]),
     "mdwf_last_error": (ctypes.c_char_p, [_P]),
@@ -110,6 +112,7 @@ _SIGS = {
     "mdwf_source_point": (_I, [_P, ctypes.POINTER(Action), ctypes.POINTER(_I), _I, _I, _P]),
     "mdwf_source_z2": (_I, [_P, ctypes.POINTER(Action), ctypes.c_uint64, _I, _P]),
     "mdwf_propagator_4d": (_I, [_P, ctypes.POINTER(Action), _I, _P, _P]),
+    "mdwf_source_physical": (_I, [_P, _P, ctypes.POINTER(Action), _I, _I, _P, _P]),
     "mdwf_current_source": (_I, [_P, ctypes.POINTER(Action), _I, _I, _P, _P]),
     "mdwf_dslash": (_I, [_P, _P, ctypes.POINTER(Action), _I, _I, _I, _P, _P]),
     "mdwf_hop_split": (_I, [_P, _P, ctypes.POINTER(Action), _I, _I, _I, _P, _P, ctypes.POINTER(ctypes.c_double)]),
@@ -152,6 +155,17 @@ def check_action(act: Action):
     buf = ctypes.create_string_buffer(256)
     st = lib().mdwf_check_action(ctypes.byref(act), buf, len(buf))
     return st, buf.value.decode()
+
+
+def query_traversal(act: Action, prec, nrhs: int = 1, cb_log2: int = 4):
+    """Host-only: (Bt, y-bands) of the stencil traversal for this action,
+    precision and RHS count (environment overrides applied)."""
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    bt, yb = _I(), _I()
+    st = lib().mdwf_query_traversal(ctypes.byref(act), p, int(nrhs), int(cb_log2), ctypes.byref(bt), ctypes.byref(yb))
+    if st != OK:
+        raise MDWFError(st, "mdwf_query_traversal: bad argument")
+    return bt.value, yb.value
 
 
 def job_footprint(act: Action, opts: CGOpts, nrhs: int) -> int:
@@ -271,6 +285,14 @@ class Context:
                                        _ptr(q, 16 * n4 * nrhs, "q"), _ptr(eta, 16 * _numel(act) * nrhs, "eta"))
         self._check(st, "mdwf_current_source")
 
+    def source_physical(self, gauge, act: Action, xi, eta, gamma_mask: int = 0, nrhs: int = 1):
+        """eta = (1 - c5 D_W) inject(Gamma xi): the 5D source whose solution,
+        read off the walls, is the physical 4D propagator S Gamma xi."""
+        n4 = _numel(act) // act.L5
+        st = lib().mdwf_source_physical(self._h, gauge.handle, ctypes.byref(act), int(nrhs), int(gamma_mask),
+                                        _ptr(xi, 16 * n4 * nrhs, "xi"), _ptr(eta, 16 * _numel(act) * nrhs, "eta"))
+        self._check(st, "mdwf_source_physical")
+
     # ---- operators ----
     def dslash(self, gauge, act: Action, op: int, prec, inp, out, nrhs: int = 1):
         p = PREC[prec] if isinstance(prec, str) else int(prec)
@@ -317,6 +339,19 @@ class Context:
         return lib().mdwf_job_step(self._h, arr, len(jobs), int(iters))
 
     # ---- measurement ----
+    def copy_bandwidth(self, src, dst, reps: int = 5) -> float:
+        """GB/s (read + write) of the library's STREAM-style copy kernel
+        moving src (a contiguous device tensor) into dst of the same size."""
+        nb = src.numel() * src.element_size()
+        if dst.numel() * dst.element_size() != nb:
+            raise ValueError("copy_bandwidth: src and dst differ in size")
+        g = ctypes.c_double()
+        st = lib().mdwf_copy_bandwidth(self._h, _ptr(src, nb, "src"), _ptr(dst, nb, "dst"), nb, int(reps),
+                                       ctypes.byref(g))
+        self._check(st, "mdwf_copy_bandwidth")
+        return g.value
+
+
     def profile_enable(self, on=True, sample: int = 1):
         """Kernel timing on/off; sample = N > 1 times one CG iteration in N."""
         mode = 0 if not on else max(int(sample), 1)

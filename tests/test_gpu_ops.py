@@ -5,21 +5,34 @@ seconds, covering several workgroup tiles, ragged tails (sites per parity not
 a multiple of 16/32/64), L5 = 1, a large L5, periodic and antiperiodic time,
 the free field, and all four storage precisions.
 
-Tolerances (norm-wise relative error): FP64 1e-13 (rounding of ~1e3 flops per
-output), FP32 2e-6, FP16 8e-3, BF16 6e-2 and int16 fixed point 1e-3 (11, 8
-and 15 significant bits of per-site-scaled storage, rounded again at every
-stored intermediate).
+Every comparison checks the norm-wise relative error |got - ref| / |ref| and
+the element-wise one max|got - ref| / max|ref| against the same bar, and logs
+both.  Bars:
+
+* FP64 1e-13: ~1e3 flops per output, each rounded at 2^-53 ~ 1.1e-16.
+* FP32 1e-6 (the dslash bar FP32 results are held to): the input is rounded
+  to FP32 once (2^-24 ~ 6e-8 relative) and each launch sums ~100 terms per
+  output in FP32; the deepest operator (M^+M^, four launches) stays below
+  ~1e-6.
+* 16-bit storage with one FP32 scale per 5D site: the storage unit roundoff u
+  is 2^-11 (FP16), 2^-8 (BF16), 1/(2*32767) (int16 of the site maximum).
+  Every stored field (the input and the output of each launch, up to five for
+  M^+M^) adds an error of at most u times the site maximum; the operators
+  between them have norm <= ~2 and the errors add in norm, so the bar is
+  16u: FP16 8e-3, BF16 6e-2, int16 1e-3 (the int16 bar 16u = 2.4e-4 is
+  raised to 1e-3 because the stored integers enter FP32 arithmetic unscaled
+  and sites far below their neighbours lose relative precision).
 """
 import numpy as np
 import pytest
 
 import mdwf_synth as S
 import oracle as O
-from gpu_util import empty_like_dev, log, make_case, rel, to_dev, to_host
+from gpu_util import check, empty_like_dev, log, make_case, rel, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-13, "f32": 2e-6, "f16": 8e-3, "bf16": 6e-2, "i16": 1e-3}
+TOL = {"f64": 1e-13, "f32": 1e-6, "f16": 8e-3, "bf16": 6e-2, "i16": 1e-3}
 
 CASES = {
     # name: (L, L5, mq, eps, seed, t_antiperiodic)
@@ -92,8 +105,7 @@ def test_op_f64(ctx, name, op):
     out = empty_like_dev(x.shape)
     ctx.dslash(g, act, getattr(M, "OP_" + op), "f64", xi, out)
     got = to_host(out)
-    err = rel(got, expect)
-    assert err < TOL["f64"], err
+    check(got, expect, TOL["f64"], f"{name} {op} f64")
     # untouched parity of half-field outputs is exactly zero
     if op in ("MHAT", "MHATDAG", "NORMAL", "HOP_EO", "PREP"):
         assert np.abs(O.parity_mask(oact, 1) * got).max() == 0.0
@@ -113,8 +125,7 @@ def test_op_low_precision(ctx, prec, name, op):
     expect = _oracle(op, U, x, oact)
     out = empty_like_dev(x.shape)
     ctx.dslash(g, act, getattr(M, "OP_" + op), prec, to_dev(x), out)
-    err = rel(to_host(out), expect)
-    assert err < TOL[prec], err
+    check(to_host(out), expect, TOL[prec], f"{name} {op} {prec}")
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16", "bf16", "i16"])
@@ -135,7 +146,10 @@ def test_op_tiny_sites(ctx, prec, op):
     ctx.dslash(g, act, getattr(M, "OP_" + op), prec, to_dev(x), out)
     got = to_host(out)
     assert np.isfinite(got).all()
+    # norm-wise only: the element-wise bar relative to the largest site is
+    # meaningless when site magnitudes span 60 decades
     err = rel(got, expect)
+    log(f"   tiny sites {op} {prec}: norm-wise {err:.2e} (bar {TOL[prec]:.0e})")
     assert err < TOL[prec], err
 
 
@@ -172,7 +186,7 @@ def test_traversal_orders_bitwise(ctx, prec, monkeypatch):
         outs.append(to_host(out))
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
-    assert rel(outs[0], _oracle("NORMAL", U, x, oact)) < TOL[prec]
+    check(outs[0], _oracle("NORMAL", U, x, oact), TOL[prec], f"traversal NORMAL {prec}")
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16", "i16"])

@@ -34,3 +34,30 @@ def test_fastdiv_bound_is_needed():
     m = _magic(d)
     n = (1 << 32) - 1
     assert n * d >= 1 << 32 and (n * m) >> 32 != n // d
+
+
+def test_traversal_overrides_are_clamped(monkeypatch):
+    """The stencil's workgroup traversal after the MDWF_BT / MDWF_YB
+    overrides: negative or non-dividing values fall back to the linear order
+    (Bt = 0) and one band, so a mistyped override can never produce
+    out-of-range site indices (host-side query, no GPU)."""
+    from paper_1810_01609_amd import mdwf as M
+
+    act = M.Action.make((32, 32, 32, 64), 12, mq=0.005)
+    monkeypatch.delenv("MDWF_BT", raising=False)
+    monkeypatch.delenv("MDWF_YB", raising=False)
+    assert M.query_traversal(act, "f16", 12) == (2, 8)  # L5 <= 12: 4-row bands, Bt = 2
+    act16 = M.Action.make((24, 24, 24, 64), 16, mq=0.01)
+    bt, yb = M.query_traversal(act16, "f16", 1)
+    assert yb == 1 and bt in (2, 4, 8) and 64 % bt == 0
+    for bt_env, yb_env, want in (("-3", "-2", (2, 8)),     # ignored: defaults stay
+                                 ("0", "1", (0, 1)),       # linear order, one band
+                                 ("3", "8", (0, 8)),       # 3 does not divide Lt = 64
+                                 ("4", "5", (4, 1)),       # 5 does not divide Ly = 32
+                                 ("8", "16", (8, 16)),     # 2-row bands: 16 x 2 = 32 sites, two workgroups
+                                 ("2", "64", (2, 1))):     # 64 bands of half a row: not whole workgroups
+        monkeypatch.setenv("MDWF_BT", bt_env)
+        monkeypatch.setenv("MDWF_YB", yb_env)
+        assert M.query_traversal(act, "f16", 12) == want, (bt_env, yb_env)
+    with __import__("pytest").raises(M.MDWFError):
+        M.query_traversal(act, "f16", 12, cb_log2=9)
