@@ -187,3 +187,60 @@ def test_profile_counts_working_launches(ctx, sample):
     lo = 4 * st["iters"] + 1
     assert lo <= d["launches"] <= lo + st["reliable_updates"], (d, st)
     assert d["ms"] > 0 and d["bytes"] > 0
+
+
+def test_graph_replay_equals_eager(ctx, monkeypatch):
+    """The CG iteration captured once into a HIP graph and replayed (between
+    the replays: the host's polls, reliable updates in FP64, the batch
+    shrinking when a RHS converges and the graph being captured again) gives
+    bitwise the solutions and iteration counts of the launches issued one by
+    one, for two jobs of different masses stepped together."""
+    from paper_1810_01609_amd import mdwf as M
+
+    U, act, oact, g, *_ = _c1(ctx)
+    acts = [M.Action.make(act.lattice, act.L5, 1.5, 0.5, 1.3, mq) for mq in (0.05, 0.1)]
+    etas = [np.stack([O.z2_source(oact, 40 + r, rhs=r) for r in range(2)]), O.point_source(oact, (1, 0, 0, 1), 2, 0)[None]]
+    outs = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("MDWF_GRAPH", mode)
+        for inner in ("f32", "f16"):
+            opts = M.CGOpts.make(tol=1e-10, inner=inner)
+            psis = [empty_like_dev(e.shape) for e in etas]
+            jobs = [ctx.job_begin(g, a, opts, to_dev(e), p, nrhs=e.shape[0]) for a, e, p in zip(acts, etas, psis)]
+            while not all(j.poll()[0] for j in jobs):
+                assert ctx.job_step(jobs, 1000) == M.OK
+            stats = [j.poll()[1] for j in jobs]
+            for j in jobs:
+                j.end()
+            outs[(mode, inner)] = ([to_host(p) for p in psis], [[s["iters"] for s in st] for st in stats])
+            log(f"[graph] MDWF_GRAPH={mode} {inner}: iterations {outs[(mode, inner)][1]}")
+    for inner in ("f32", "f16"):
+        (pa, ia), (pb, ib) = outs[("0", inner)], outs[("1", inner)]
+        assert ia == ib
+        for x, y in zip(pa, pb):
+            assert np.array_equal(x, y)
+    # and the solutions are right
+    psi_o, _ = O.solve(U, etas[1][0], O.Action(act.lattice, act.L5, 1.5, 0.5, 1.3, 0.1), tol=1e-12)
+    assert rel(outs[("1", "f32")][0][1][0], psi_o) < 1e-8
+
+
+def test_many_reliable_updates(ctx):
+    """delta = 0.9 forces a reliable update nearly every iteration: four fused
+    RHS make several hundred updates in one step call, so the small-table
+    region the updates upload through wraps around several times while the
+    CG loop keeps reading its own tables from it; every solution still
+    matches the oracle's."""
+    from paper_1810_01609_amd import mdwf as M
+
+    U, act, oact, g, *_ = _c1(ctx)
+    etas = np.stack([O.z2_source(oact, 60 + r, rhs=r) for r in range(4)])
+    psi = empty_like_dev(etas.shape)
+    stats = ctx.solve(g, act, M.CGOpts.make(tol=1e-10, inner="f32", delta=0.9), to_dev(etas), psi, nrhs=4)
+    got = to_host(psi)
+    total = sum(s["reliable_updates"] for s in stats)
+    log(f"[solve] delta 0.9: {total} reliable updates, iterations {[s['iters'] for s in stats]}")
+    assert total > 150
+    for r in range(4):
+        assert stats[r]["converged"] == 1
+        psi_o, _ = O.solve(U, etas[r], oact, tol=1e-12)
+        assert rel(got[r], psi_o) < 1e-8
