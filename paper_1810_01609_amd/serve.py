@@ -238,6 +238,7 @@ class GPUBackend:
             U = S.gauge_field(V, gauge_eps, seeds.get(V, 11 + i))
             self.gauge[V] = self.ctx0.gauge_load(V, U, precs=("f64", inner))
         self.lane_ctx = {}
+        self.lane_streams = {}
         self.lock = threading.Lock()
 
     @property
@@ -256,25 +257,49 @@ class GPUBackend:
         return self.M.job_footprint(self.act(req), self.opts(), req.nsrc) + 2 * user
 
     def ctx_for(self, lane):
+        """The lane's context, on a stream of its own: a torch stream (created
+        non-blocking, default priority), so the lane's work never waits for
+        torch's default stream or for another lane."""
+        import torch
+
         with self.lock:
             if lane not in self.lane_ctx:
-                self.lane_ctx[lane] = self.M.Context(self.device, use_torch_stream=False)
+                s = torch.cuda.Stream(device=f"cuda:{self.device}")
+                self.lane_streams[lane] = s
+                self.lane_ctx[lane] = self.M.Context(self.device, stream=s.cuda_stream)
             return self.lane_ctx[lane]
+
+    def lane_stream(self, lane):
+        """The lane's torch stream (the one its context adopted)."""
+        self.ctx_for(lane)
+        return self.lane_streams[lane]
 
     def begin(self, req):
         import torch
 
         ctx = self.ctx_for(req.lane)
         a = self.act(req)
-        eta = torch.zeros((req.nsrc,) + a.spinor_shape(), dtype=torch.complex128, device=f"cuda:{self.device}")
-        psi = torch.zeros_like(eta)
-        torch.cuda.synchronize(self.device)
+        # the request's tensors are allocated and cleared on the lane's own
+        # stream, so the library's kernels that follow on that stream are
+        # ordered after the clearing without waiting for any other lane
+        with torch.cuda.stream(self.lane_stream(req.lane)):
+            eta = torch.zeros((req.nsrc,) + a.spinor_shape(), dtype=torch.complex128, device=f"cuda:{self.device}")
+            psi = torch.zeros_like(eta)
         for k in range(req.nsrc):
             ctx.source_z2(a, req.seed, req.src_offset + k, eta[k])
         job = ctx.job_begin(self.gauge[tuple(req.volume)], a, self.opts(), eta, psi, nrhs=req.nsrc)
         job.req = req
         job.psi = psi
         return job
+
+    def solution(self, lane, job):
+        """The finished job's psi on the host (waits for the lane's stream only)."""
+        import torch
+
+        s = self.lane_stream(lane)
+        s.synchronize()
+        with torch.cuda.stream(s):
+            return job.psi.cpu().numpy()
 
     def step(self, lane, jobs, iters):
         ctx = self.ctx_for(lane)
@@ -299,9 +324,10 @@ class GPUBackend:
 
 
 def serve_gpu(trace, backend: GPUBackend, budget_bytes, iters_per_step=25, max_slots_per_lane=24,
-              keep_solutions=False):
+              keep_solutions=False, progress=None):
     """Serve a trace in real time: arrivals at their t_arrival (seconds from
-    start), one worker thread per lane."""
+    start), one worker thread per lane.  progress(done, total, seconds) is
+    called about every 10 s."""
     sched = Scheduler(budget_bytes, backend.footprint, max_slots_per_lane)
     pending = deque(sorted(trace, key=lambda r: r.t_arrival))
     handles = {}
@@ -331,10 +357,7 @@ def serve_gpu(trace, backend: GPUBackend, budget_bytes, iters_per_step=25, max_s
                     if done:
                         h = handles.pop(r.id)
                         if keep_solutions:
-                            import torch
-
-                            torch.cuda.synchronize(backend.device)
-                            solutions[r.id] = h.psi.cpu().numpy()
+                            solutions[r.id] = backend.solution(lane, h)
                         backend.end(h)
                         sched.retire(r, now(), stats)
                         with wake:
@@ -344,7 +367,11 @@ def serve_gpu(trace, backend: GPUBackend, budget_bytes, iters_per_step=25, max_s
             stop.set()
 
     n_total = len(pending)
+    t_report = 0.0
     while len(sched.done) < n_total and not stop.is_set():
+        if progress is not None and now() - t_report >= 10.0:
+            t_report = now()
+            progress(len(sched.done), n_total, t_report)
         while pending and pending[0].t_arrival <= now():
             sched.arrive(pending.popleft())
         for r in sched.admit(now()):
@@ -362,3 +389,47 @@ def serve_gpu(trace, backend: GPUBackend, budget_bytes, iters_per_step=25, max_s
     if errors:
         raise errors[0]
     return sched, solutions, now()
+
+
+def serve_fifo(trace, backend: GPUBackend, keep_solutions=False, progress=None):
+    """The plain baseline: requests in arrival order, one right-hand side at a
+    time, each a complete single-RHS solve in the backend's inner precision
+    (FP64 for the baseline) on one context -- no batching, no overlap.  A
+    request that arrives while the GPU is busy waits in the queue."""
+    import torch
+
+    M = backend.M
+    ctx = backend.ctx_for(("fifo", 0))
+    stream = backend.lane_stream(("fifo", 0))
+    order = sorted(trace, key=lambda r: r.t_arrival)
+    solutions = {}
+    t0 = time.perf_counter()
+    now = lambda: time.perf_counter() - t0
+    done = []
+    t_report = 0.0
+    for r in order:
+        if progress is not None and now() - t_report >= 10.0:
+            t_report = now()
+            progress(len(done), len(order), t_report)
+        while now() < r.t_arrival:
+            time.sleep(min(0.001, r.t_arrival - now()))
+        r.t_admit = now()
+        a = backend.act(r)
+        with torch.cuda.stream(stream):
+            eta = torch.zeros(a.spinor_shape(), dtype=torch.complex128, device=f"cuda:{backend.device}")
+            psi = torch.zeros_like(eta)
+        stats, sols = [], []
+        for k in range(r.nsrc):
+            ctx.source_z2(a, r.seed, r.src_offset + k, eta)
+            stats.extend(ctx.solve(backend.gauge[tuple(r.volume)], a, backend.opts(), eta, psi, raise_on_fail=False))
+            if keep_solutions:
+                stream.synchronize()
+                with torch.cuda.stream(stream):
+                    sols.append(psi.cpu().numpy())
+        stream.synchronize()
+        r.t_done = now()
+        r.stats = stats
+        done.append(r)
+        if keep_solutions:
+            solutions[r.id] = sols
+    return done, solutions, now()
