@@ -1,21 +1,24 @@
 """Benchmark: Moebius domain-wall propagator solves on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4]
 
-One step is one pass of the whole solve path over one right-hand side of the
-workload: complex Z2 source generated on the device, even-odd source
-preparation, mixed-precision CG (FP32 inner iteration with FP64 reliable
-updates and FP64 reductions) to |b - A x| <= 1e-10 |b|, reconstruction of the
-odd half and the FP64 full-5D residual check.  The gauge field is resident
-in HBM before timing starts.  `value` is solves per second over the timed
-steps; the JSON line also carries the per-step latency percentiles, the
-plain FP64 solver on the same input, the fused stencil kernel's roofline
-(algorithmic bytes per launch / its average HIP-event duration, the events
-riding in the kernel dispatches of one CG iteration in 13) and the CPU
-oracle's rate on a bounded sample of the same workload.
-
-The workload (default c2): lattice 16^3 x 32, L5 = 12, b5 = 1.5, c5 = 0.5,
-M5 = 1.3, m_q = 0.02, links exp(i 0.2 H) seed 2, Z2 source seed 1002.
+Default workload (c4, the largest configuration, quoted in RHS/s): lattice
+32^3 x 64, L5 = 12, b5 = 1.5, c5 = 0.5, M5 = 1.3, m_q = 0.005, links
+exp(i 0.15 H) seed 4, the 12 spin-colour point sources at the origin.  One
+step is one pass of the whole solve path over that batch: the 12 sources
+generated on the device, even-odd source preparation, one fused 12-RHS
+mixed-precision CG (FP16 storage with per-site scales, FP32 arithmetic, FP64
+reliable updates and reductions) to |b - A x| <= 1e-10 |b| for every RHS,
+reconstruction of the odd half and the FP64 full-5D residual check.  The
+gauge field is resident in HBM before timing starts.  `value` is solved
+right-hand sides per second over the timed steps; the JSON line also carries
+the per-step latency percentiles, the plain FP64 single-RHS solver on the
+same input, the fused stencil kernel's roofline (algorithmic bytes per launch
+/ its average HIP-event duration, the events riding in the kernel dispatches
+of one CG iteration in 13), the library's STREAM-style copy rate measured in
+the same run, and the CPU oracle's rate on a bounded sample of the workload.
+Other workloads (c1, c2, c3, c5 serving) and modes (--dslash-only, --fh,
+--split) are selected by flags.
 """
 from __future__ import annotations
 
@@ -58,19 +61,32 @@ def measured_traffic(workload: str):
 def cpu_baseline(cfg, gpu_iters_f64: int):
     """The oracle as it stands, timed on a bounded sample of the workload.
 
-    Each of the oracle's building blocks is applied once to a field on the
-    full lattice (one 4D hop H, one M5^-1, one M_phi: ~30 s of CPU work);
-    the solve time is then composed from how often the oracle's even-odd
-    CGNR calls them: per iteration 4 hops, 4 M5^-1 and 4 M_phi (M^ and M^+),
-    plus setup (source preparation and b = M^+ eta^: 3 hops, 4 M5^-1,
-    3 M_phi), times the FP64 iteration count of the same solve.
+    Each of the oracle's building blocks is applied once to a field (one 4D
+    hop H, one M5^-1, one M_phi: ~10-30 s of CPU work in all).  Up to 2M 5D
+    sites the field covers the whole lattice; beyond, a slab of the lattice
+    (the full Lx, Ly, Lz and the fewest time slices that still hold ~1.5M 5D
+    sites, with the workload's L5) stands in for it, and the times are scaled
+    by the volume ratio (the oracle's cost per site does not depend on the
+    volume: every step is a whole-array NumPy operation).  The solve time is
+    then composed from how often the oracle's even-odd CGNR calls them: per
+    iteration 4 hops, 4 M5^-1 and 4 M_phi (M^ and M^+), plus setup (source
+    preparation and b = M^+ eta^: 3 hops, 4 M5^-1, 3 M_phi), times the FP64
+    iteration count of the same solve on the GPU.  One right-hand side.
     """
     import mdwf_synth as S
     import oracle as O
 
-    act = O.Action(cfg["L"], cfg["L5"], cfg["b5"], cfg["c5"], cfg["M5"], cfg["mq"])
-    U = S.gauge_field(cfg["L"], cfg["eps"], cfg["seed"])
-    x = S.random_spinor(cfg["L"], cfg["L5"], 7)
+    L = list(cfg["L"])
+    L5 = cfg["L5"]
+    v5 = L[0] * L[1] * L[2] * L[3] * L5
+    scale = 1.0
+    if v5 > 2_000_000:
+        lt = max(2, int(1.5e6 / (L[0] * L[1] * L[2] * L5)) // 2 * 2)
+        scale = L[3] / lt
+        L[3] = lt
+    act = O.Action(tuple(L), L5, cfg["b5"], cfg["c5"], cfg["M5"], cfg["mq"])
+    U = S.gauge_field(tuple(L), cfg["eps"], cfg["seed"])
+    x = S.random_spinor(tuple(L), L5, 7)
     t = {}
     from threadpoolctl import threadpool_limits
 
@@ -79,19 +95,22 @@ def cpu_baseline(cfg, gpu_iters_f64: int):
                          ("m_phi", lambda: O.m_phi(x, act))):
             t0 = time.perf_counter()
             fn()
-            t[name] = time.perf_counter() - t0
+            t[name] = (time.perf_counter() - t0) * scale
     per_iter = 4 * t["hop"] + 4 * t["m5_inv"] + 4 * t["m_phi"]
     setup = 3 * t["hop"] + 4 * t["m5_inv"] + 3 * t["m_phi"]
     t_solve = setup + per_iter * gpu_iters_f64
+    where = (f"the full {cfg['L'][0]}^3x{cfg['L'][3]} L5={L5} lattice" if scale == 1.0 else
+             f"a {L[0]}x{L[1]}x{L[2]}x{L[3]} L5={L5} slab of the {cfg['L'][0]}^3x{cfg['L'][3]} lattice, "
+             f"times scaled by {scale:g} to the whole volume")
     return {
         "value": 1.0 / t_solve,
         "unit": "solves/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"oracle hop, M5^-1 and M_phi each applied once (NumPy FP64, one thread) on the full "
-                   f"{cfg['L'][0]}^3x{cfg['L'][3]} L5={cfg['L5']} lattice; solve time composed as setup + "
-                   f"{gpu_iters_f64} CGNR iterations x (4 hop + 4 M5^-1 + 4 M_phi), the oracle's own call "
-                   f"counts, with the FP64 iteration count of the same solve"),
+        "sample": (f"oracle hop, M5^-1 and M_phi each applied once (NumPy FP64, one thread) on {where}; solve time "
+                   f"(one RHS) composed as setup + {gpu_iters_f64} CGNR iterations x (4 hop + 4 M5^-1 + 4 M_phi), "
+                   f"the oracle's own call counts, with the FP64 iteration count of the same solve"),
+        "estimate": scale != 1.0,
         "component_seconds": t,
         "seconds_per_iteration": per_iter,
         "host_cpus": os.cpu_count(),
@@ -108,6 +127,11 @@ def _cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
+
+
+def progress(msg):
+    """A progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def stats_flops(stats, nrhs):
@@ -140,12 +164,22 @@ def fh_bench(args):
     fh = torch.zeros_like(eta)
     opts = M.CGOpts.make(tol=1e-10, inner=inner)
 
+    xi = torch.zeros_like(q)
+
     def step():
         seed = cfg["z2_seed"] if cfg["source"] == "z2" else 1
         ctx.source_z2(act, seed, 0, eta)
+        if args.physical:
+            # the 4D noise itself (reading the walls back inverts the injection),
+            # then the physical source (1 - c5 D_W) inject(xi)
+            ctx.propagator_4d(act, eta, xi)
+            ctx.source_physical(g, act, xi, eta)
         s1 = ctx.solve(g, act, opts, eta, psi)[0]
         ctx.propagator_4d(act, psi, q)
-        ctx.current_source(act, 11, q, eta2)
+        if args.physical:
+            ctx.source_physical(g, act, q, eta2, gamma_mask=11)
+        else:
+            ctx.current_source(act, 11, q, eta2)
         s2 = ctx.solve(g, act, opts, eta2, fh)[0]
         return s1, s2
 
@@ -164,7 +198,8 @@ def fh_bench(args):
         "value": args.steps / el if ok else 0.0, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if inner == "f64" else "f32", "data": "synthetic",
-        "config": {"workload": f"{args.workload} Feynman-Hellmann: Z2 source, axial current g_x g_y g_t, {inner} inner"},
+        "config": {"workload": (f"{args.workload} Feynman-Hellmann: Z2 source, axial current g_x g_y g_t, {inner} inner"
+                                + (", physical 4D propagators (Moebius source factor)" if args.physical else ""))},
         "iters": [stats[-1][0]["iters"], stats[-1][1]["iters"]],
         "rel_res_full": [stats[-1][0]["rel_res_full"], stats[-1][1]["rel_res_full"]],
     }
@@ -229,25 +264,46 @@ def split_bench(args):
 
 
 def serve_bench(args):
-    """c5: a Poisson stream of solves served with continuous batching."""
+    """c5: a Poisson stream of solves served with continuous batching in the
+    mixed precision, then (with --fifo-baseline) the same trace served by the
+    plain baseline: first in, first out, one right-hand side at a time, FP64
+    CG.  Both report p50/p99 latency and solved right-hand sides per second."""
     import mdwf_synth as S
-    from paper_1810_01609_amd.serve import GPUBackend, Request, merge_chunks, percentiles, serve_gpu, split_requests
+    from paper_1810_01609_amd.serve import (GPUBackend, Request, merge_chunks, percentiles, serve_fifo, serve_gpu,
+                                            split_requests)
 
     vols = [(8, 8, 8, 16), (16, 16, 16, 32), (24, 24, 24, 48), (32, 32, 32, 64)]
     trace = S.poisson_trace(args.requests, args.rate, 5, vols, [8, 12, 16], (0.005, 0.05), (1, 12))
-    reqs = [Request(id=d["id"], t_arrival=d["t_arrival"], volume=d["volume"], L5=d["L5"], mq=d["mq"],
-                    nsrc=d["nsrc"], seed=100000 + d["id"]) for d in trace]
-    parts = split_requests(reqs, args.max_rhs)
+
+    def make_reqs():
+        return [Request(id=d["id"], t_arrival=d["t_arrival"], volume=d["volume"], L5=d["L5"], mq=d["mq"],
+                        nsrc=d["nsrc"], seed=100000 + d["id"]) for d in trace]
+
+    def report(kind):
+        return lambda k, n, t: progress(f"{kind}: {k}/{n} done after {t:.0f} s")
+
     inner = args.inner or "f16"
-    be = GPUBackend(vols, gauge_eps=0.2, gauge_seeds={v: 11 + i for i, v in enumerate(vols)}, inner=inner)
+    seeds = {v: 11 + i for i, v in enumerate(vols)}
+    be = GPUBackend(vols, gauge_eps=0.2, gauge_seeds=seeds, inner=inner)
     budget = int(args.hbm_budget_gb * 1e9) - be.resident_bytes
-    sched, _, wall = serve_gpu(parts, be, budget, iters_per_step=args.iters_per_step,
-                               max_slots_per_lane=args.max_slots)
+    sched, _, wall = serve_gpu(split_requests(make_reqs(), args.max_rhs), be, budget,
+                               iters_per_step=args.iters_per_step, max_slots_per_lane=args.max_slots,
+                               progress=report("continuous batching"))
     be.close()
     done = merge_chunks(sched.done)
     nrhs = sum(r.nsrc for r in done)
     ok = all(s.get("converged") == 1 for r in done for s in r.stats)
     p = percentiles(done)
+    base = None
+    if args.fifo_baseline:
+        be64 = GPUBackend(vols, gauge_eps=0.2, gauge_seeds=seeds, inner="f64")
+        fdone, _, fwall = serve_fifo(make_reqs(), be64, progress=report("FP64 FIFO"))
+        be64.close()
+        fn = sum(r.nsrc for r in fdone)
+        fok = all(s.get("converged") == 1 for r in fdone for s in r.stats)
+        base = {"solves_per_s": fn / fwall if fok else 0.0, "latency_ms": percentiles(fdone), "wall_s": fwall,
+                "rhs_completed": fn, "converged_all": fok,
+                "kind": "FP64 CG, one right-hand side at a time, requests first in first out"}
     line = {
         "metric": "MDWF CG solves/s at rel-res 1e-10; Dslash HBM GB/s; p50/p99 solve latency",
         "value": nrhs / wall if ok else 0.0,
@@ -255,12 +311,13 @@ def serve_bench(args):
         "n_gpus": 1, "steps": len(done), "warmup": 0, "ms_per_step": 1e3 * wall / max(len(done), 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if inner == "f64" else "f32",
         "data": "synthetic",
-        "config": {"workload": (f"c5: Poisson stream of {args.requests} requests at {args.rate}/s over volumes "
-                                f"{vols}, L5 in {{8,12,16}}, mq U[0.005,0.05], 1-12 Z2 sources, "
+        "config": {"workload": (f"c5: Poisson stream of {args.requests} requests at {args.rate}/s (trace seed 5) over "
+                                f"volumes {vols}, L5 in {{8,12,16}}, mq U[0.005,0.05], 1-12 Z2 sources, "
                                 f"chunks of <= {args.max_rhs} RHS, {inner} inner, continuous batching"),
                    "budget_gb": budget / 1e9},
         "latency_ms": p,
         "rhs_completed": nrhs, "wall_s": wall, "peak_hbm_gb": sched.peak_used / 1e9, "converged_all": ok,
+        "fifo_fp64_baseline": base,
     }
     print(json.dumps(line), flush=True)
 
@@ -331,11 +388,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c4")
     ap.add_argument("--inner", default=None, help="inner precision (default: f32 for c1/c2, f16 for c3/c4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-f64", action="store_true", help="skip the plain FP64 reference solve (profiling runs)")
-    ap.add_argument("--requests", type=int, default=12, help="c5: requests in the trace")
+    ap.add_argument("--requests", type=int, default=200, help="c5: requests in the trace")
+    ap.add_argument("--fifo-baseline", action="store_true",
+                    help="c5: also serve the trace first-in-first-out, one RHS at a time, in FP64")
     ap.add_argument("--rate", type=float, default=20.0, help="c5: mean arrivals per second")
     ap.add_argument("--max-rhs", type=int, default=4, help="c5: largest chunk of sources admitted at once")
     ap.add_argument("--max-slots", type=int, default=16, help="c5: largest fused batch per lane")
@@ -353,6 +412,8 @@ def main():
                          "last (default by inner precision: 3e-4 for f32, 0.3 for bf16, 0.1 for f16 and i16)")
     ap.add_argument("--check-every", type=int, default=8, help="CG iterations between host polls of the solver state")
     ap.add_argument("--fh", action="store_true", help="Feynman-Hellmann propagator pairs instead of single solves")
+    ap.add_argument("--physical", action="store_true",
+                    help="--fh: physical 4D propagators (sources (1 - c5 D_W) inject(xi), opposite walls)")
     ap.add_argument("--split", action="store_true",
                     help="one rank's share of the workload split 2x2x2 in (y, z, t): face packing, interior and "
                          "exterior hop against the plain hop of the same block")
@@ -371,13 +432,17 @@ def main():
     import torch
 
     if args.copy_calibration:
-        n = 1 << 28  # 2 GiB of float64
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        # the library's copy kernel on 2 GiB each way: HBM counters of its
+        # dispatches calibrate those of the stencil
+        from paper_1810_01609_amd import mdwf as M
+
+        n = 1 << 27  # 2 GiB of complex128
+        src = torch.ones(n, dtype=torch.complex128, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_each_way": n * 8, "launches": 5}))
+        ctx = M.Context(0)
+        gbs = ctx.copy_bandwidth(src, dst, reps=4)
+        ctx.close()
+        print(json.dumps({"copy_bytes_each_way": n * 16, "launches": 5, "GB_per_s": gbs}))
         return
 
     if args.workload == "c5":
@@ -402,8 +467,17 @@ def main():
     L, L5 = cfg["L"], cfg["L5"]
     nrhs = 12 if cfg["source"] == "point12" else 1
     act = M.Action.make(L, L5, cfg["b5"], cfg["c5"], cfg["M5"], cfg["mq"])
+    t_start = time.perf_counter()
     U = S.gauge_field(L, cfg["eps"], cfg["seed"])
+    progress(f"gauge field generated ({time.perf_counter() - t_start:.1f} s)")
     ctx = M.Context(0)
+    # achievable bandwidth in this run: the library's STREAM-style copy of 4 GiB
+    a = torch.ones(1 << 28, dtype=torch.complex128, device="cuda")
+    b = torch.empty_like(a)
+    copy_gbs = ctx.copy_bandwidth(a, b, reps=10)
+    del a, b
+    torch.cuda.empty_cache()
+    progress(f"copy kernel {copy_gbs:.0f} GB/s")
     g = ctx.gauge_load(L, U, precs=("f64", args.inner))
     del U
     eta = torch.zeros((nrhs,) + act.spinor_shape(), dtype=torch.complex128, device="cuda")
@@ -435,9 +509,13 @@ def main():
         st64 = step(opts64, 1)[0]
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t
+        progress(f"plain FP64 single-RHS solve: {t64:.2f} s, {st64['iters']} iterations")
 
-    for _ in range(args.warmup):
+    for w in range(args.warmup):
+        t = time.perf_counter()
         step(opts)
+        torch.cuda.synchronize()
+        progress(f"warm-up step {w + 1}/{args.warmup}: {time.perf_counter() - t:.2f} s")
     torch.cuda.synchronize()
     # kernel timing: every launch outside the CG loop and every launch of one
     # CG iteration in 13 (start/stop events inside the dispatches; 13 is prime
@@ -450,10 +528,11 @@ def main():
     stats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         ts = time.perf_counter()
         stats.extend(step(opts))
         lat.append(time.perf_counter() - ts)
+        progress(f"step {k + 1}/{args.steps}: {lat[-1]:.2f} s")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = {k: ctx.profile_read(c) for k, c in
@@ -487,6 +566,7 @@ def main():
                          f"seed {cfg['seed']}, {cfg['source']} source, even-odd CGNR to 1e-10, "
                          f"{args.inner} inner + f64 reliable updates"),
             "lattice": list(L), "L5": L5, "nrhs": nrhs, "inner": args.inner, "tol": 1e-10, "delta": opts.delta,
+            "storage": args.inner, "arithmetic": "f64" if args.inner == "f64" else "f32",
         },
         "roofline": {
             "bound": "hbm",
@@ -501,6 +581,9 @@ def main():
             "launches": d["launches"],
             "traffic_note": traffic_note,
             "cache_resident": bool(cfg["L"][0] * cfg["L"][1] * cfg["L"][2] * cfg["L"][3] * L5 * 48 < 256e6),
+            "copy_GBs": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs if achieved and copy_gbs else None,
+            "copy_note": "the library's STREAM-style copy kernel (mdwf_copy_bandwidth), 4 GiB, measured in this run",
         },
         "tflops": (stats_flops(stats, nrhs) / elapsed / 1e12) if ok else None,
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
@@ -515,7 +598,8 @@ def main():
                          "rel_res_full": st64["rel_res_full"]},
         "kernel_time_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()},
     }
-    if not args.no_cpu_baseline and not args.skip_f64 and args.workload in ("c1", "c2"):
+    if not args.no_cpu_baseline and not args.skip_f64:
+        progress("timing the CPU oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(cfg, st64["iters"])
     g.free()
     ctx.close()
