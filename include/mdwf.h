@@ -306,9 +306,18 @@ MDWF_API mdwf_status mdwf_hop_split(mdwf_ctx *ctx, const mdwf_gauge *g, const md
  * most work in low precision, occasional reliable updates to FP64).  All
  * RHS run fused through the same kernels.  Blocks until every RHS has
  * finished; fills stats[nrhs].  Returns MDWF_OK if all converged, otherwise
- * the first failing RHS's status (the others' results are still written). */
+ * the first failing RHS's status (the others' results are still written).
+ * The solver state (mdwf_job_footprint bytes) stays allocated in the
+ * context after the call and is reused by the context's next mdwf_solve of
+ * the same or a smaller size (MDWF_SOLVE_CACHE=0 frees it at once;
+ * mdwf_trim or mdwf_destroy release it). */
 MDWF_API mdwf_status mdwf_solve(mdwf_ctx *ctx, const mdwf_gauge *g, const mdwf_action *act, const mdwf_cg_opts *opts,
                        int32_t nrhs, const void *eta, void *psi, mdwf_cg_stats *stats);
+
+/* Release the device memory the context keeps between calls (the last
+ * solve's state, the operator and FP64 workspaces); the next call that needs
+ * them allocates again.  Waits for the context stream.  EINVAL on NULL. */
+MDWF_API mdwf_status mdwf_trim(mdwf_ctx *ctx);
 
 /* ---- stepping interface for continuous batching --------------------------- */
 

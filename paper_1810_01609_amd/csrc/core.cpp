@@ -65,11 +65,6 @@ mdwf_status check_action_msg(const mdwf_action* a, std::string& msg) {
     msg = "L5 must be in [1, 32]";
     return MDWF_EINVAL;
   }
-  // field locations are 32-bit counts of 16-byte groups (12 per FP64 site)
-  if ((v4 / 2 + 16.0) * a->L5 * 12.0 >= 4294967296.0) {
-    msg = "lattice too large (V4/2 * L5 * 12 must stay below 2^32)";
-    return MDWF_EINVAL;
-  }
   if (!std::isfinite(a->b5) || !std::isfinite(a->c5) || !std::isfinite(a->M5) || !std::isfinite(a->mq)) {
     msg = "b5, c5, M5, mq must be finite";
     return MDWF_EINVAL;
@@ -379,15 +374,7 @@ static int default_stage() {
 // 8), and the traversal of the hop kernels: Bt + 1 (bits 12-15) and the y-band
 // count (bits 16-23), where 0 keeps the size-based default.  The traversal
 // only reorders whole workgroups, so every candidate gives the same result.
-constexpr int kTravBtShift = 12, kTravYbShift = 16, kNrwShift = 24;
-
-// RHS per workgroup of the untuned launch (MDWF_NRW overrides): 1
-static int default_nrw(int nslots) {
-  int n = 1;
-  const char* e = getenv("MDWF_NRW");
-  if (e != nullptr && e[0] != 0 && atoi(e) >= 1) n = atoi(e);
-  return std::min(n, std::max(nslots, 1));
-}
+constexpr int kTravBtShift = 12, kTravYbShift = 16;
 
 static void candidates(const Geom& g, int prec, DslashArgs A, bool hop, std::vector<int>& out, int& dflt) {
   out.clear();
@@ -403,33 +390,32 @@ static void candidates(const Geom& g, int prec, DslashArgs A, bool hop, std::vec
       for (int yb : ybs) trav.push_back(((bt + 1) << kTravBtShift) | (yb << kTravYbShift));
     }
   }
-  // RHS per workgroup: the default first, then 2, 3, 4 (hop kernels of a
-  // fused batch only: the staged links are what they share)
-  std::vector<int> nrws{default_nrw(A.nslots)};
-  if (hop)
-    for (int n : {1, 2, 3, 4})
-      if (n <= A.nslots && n != nrws[0]) nrws.push_back(n);
-  for (int nrw : nrws) {
-    A.nrw = nrw;
-    for (int lg = 4; lg <= 7; ++lg) {
-      const int CB = 1 << lg;
-      if (CB * g.L5 * nrw > dslash_max_threads(prec)) break;
-      if (CB > 2 * g.Vh && lg > 4) break;
-      const size_t lds = dslash_lds_bytes(A, prec, lg, hop);
-      if (lds > 160 * 1024) break;
-      for (int t : trav) out.push_back(lg | (stage << 8) | t | (nrw << kNrwShift));
-    }
+  for (int lg = 4; lg <= 7; ++lg) {
+    const int CB = 1 << lg;
+    if (CB * g.L5 > dslash_max_threads(prec)) break;
+    if (CB > 2 * g.Vh && lg > 4) break;
+    const size_t lds = dslash_lds_bytes(A, prec, lg, hop);
+    if (lds > 160 * 1024) break;
+    for (int t : trav) out.push_back(lg | (stage << 8) | t);
   }
   // untuned default: the smallest workgroup (16 sites x L5 slices) — it packs
   // the most resident waves per CU under the LDS and register limits, and the
   // tuner picks it for nearly every kernel and lattice measured — with the
-  // size-based traversal
+  // size-based traversal.  MDWF_CB_LOG2 (4..7) picks another workgroup width
+  // for the untuned launch when the kernel admits it (so every candidate the
+  // tuner may choose can be run and checked on its own).
   if (!out.empty()) dflt = out.front();
+  const char* e = getenv("MDWF_CB_LOG2");
+  if (e != nullptr && e[0] != 0)
+    for (int code : out)
+      if ((code & 0xff) == atoi(e) && (code >> kTravBtShift) == 0) {
+        dflt = code;
+        break;
+      }
 }
 
 static void apply_candidate(DslashArgs& A, int code) {
   A.stage = (code >> 8) & 1;
-  A.nrw = std::max(1, (code >> kNrwShift) & 0xf);
   const int bt1 = (code >> kTravBtShift) & 0xf;
   const int yb = (code >> kTravYbShift) & 0xff;
   if (bt1 != 0) A.order_bt = bt1 - 1;
@@ -599,6 +585,16 @@ mdwf_status mdwf_create(int32_t device, void* stream, mdwf_ctx** out) {
   return MDWF_OK;
 }
 
+mdwf_status mdwf_trim(mdwf_ctx* c) {
+  if (c == nullptr) return MDWF_EINVAL;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  release(c->job_cache);
+  release(c->dws);
+  for (auto& b : c->tmp64) release(b);
+  return MDWF_OK;
+}
+
 mdwf_status mdwf_destroy(mdwf_ctx* c) {
   if (c == nullptr) return MDWF_EINVAL;
   (void)hipSetDevice(c->device);
@@ -618,6 +614,7 @@ mdwf_status mdwf_destroy(mdwf_ctx* c) {
   release(c->red_out);
   for (auto& b : c->tmp64) release(b);
   release(c->dws);
+  release(c->job_cache);
   if (c->red_host != nullptr) (void)hipHostFree(c->red_host);
   if (c->st_host != nullptr) (void)hipHostFree(c->st_host);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -922,7 +919,7 @@ mdwf_status mdwf_tune_load(mdwf_ctx* c, const char* path) {
     float ms = 0;
     rest >> lg >> ms;
     if ((lg & 0xff) >= 4 && (lg & 0xff) <= 7 && ((lg >> 9) & 7) == 0 && ((lg >> kTravBtShift) & 0xf) <= 9 &&
-        ((lg >> kNrwShift) & 0xf) <= 4 && (lg >> 28) == 0) {
+        (lg >> 24) == 0) {
       c->tune[line.substr(0, bar)] = lg;
       c->tune_ms[line.substr(0, bar)] = ms;
     }

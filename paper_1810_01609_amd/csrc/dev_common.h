@@ -55,30 +55,6 @@ __host__ __device__ __forceinline__ size_t tile_scale_index(int cb, int s, int L
   return ((size_t)(cb / kSiteTile) * L5 + s) * kSiteTile + (cb % kSiteTile);
 }
 
-// Where one (site, slice) of a spinor field lives: g = index of its group 0
-// in 16-byte units, s = index of its per-site scale (16-bit fields).  Both
-// fit 32 bits (the action check bounds V4/2 * L5 * 12 below 2^32); the
-// address is formed once in 64 bits and the constant group offsets become
-// immediate offsets of the loads.
-struct Loc {
-  uint32_t g, s;
-};
-__host__ __device__ __forceinline__ Loc spinor_loc(int cb, int s, int L5, int G) {
-  const uint32_t ts = (uint32_t)(cb / kSiteTile) * (uint32_t)L5 + (uint32_t)s;
-  const uint32_t lane = (uint32_t)(cb % kSiteTile);
-  return Loc{ts * (uint32_t)(G * kSiteTile) + lane, ts * (uint32_t)kSiteTile + lane};
-}
-// the same site on slice s + ds
-__host__ __device__ __forceinline__ Loc loc_slice(Loc l, int ds, int G) {
-  return Loc{l.g + (uint32_t)(ds * G * kSiteTile), l.s + (uint32_t)(ds * kSiteTile)};
-}
-template <class T> __host__ __device__ __forceinline__ const T* at16(const char* base, uint32_t g) {
-  return reinterpret_cast<const T*>(base + ((size_t)g << 4));
-}
-template <class T> __host__ __device__ __forceinline__ T* at16(char* base, uint32_t g) {
-  return reinterpret_cast<T*>(base + ((size_t)g << 4));
-}
-
 // Byte offset of the per-site scale array inside a 16-bit spinor field.
 __host__ __device__ __forceinline__ size_t half_scale_offset(int L5, int Vh) {
   return round_up((size_t)L5 * padded_vh(Vh) * 48u, 256u);
@@ -272,9 +248,8 @@ template <int P> struct SpinorIO;
 
 template <> struct SpinorIO<F64> {
   using R = double;
-  static constexpr int G = 12;
-  static __device__ __forceinline__ void load_at(const char* base, const FieldDesc&, Loc l, R v[24]) {
-    const double2* p = at16<double2>(base, l.g);
+  static __device__ __forceinline__ void load(const char* base, const FieldDesc& f, int cb, int s, R v[24]) {
+    const double2* p = reinterpret_cast<const double2*>(base) + tile_index(cb, s, 0, f.L5, 12);
 #pragma unroll
     for (int g = 0; g < 12; ++g) {
       const v2d d = ldg<v2d>(p + (size_t)g * kSiteTile);
@@ -283,8 +258,8 @@ template <> struct SpinorIO<F64> {
     }
   }
   // h = 0: comps 0..5 (spins 0,1); h = 1: comps 6..11 (spins 2,3)
-  static __device__ __forceinline__ void load_half_at(const char* base, const FieldDesc&, Loc l, int h, R v[12]) {
-    const double2* p = at16<double2>(base, l.g) + (size_t)(6 * h) * kSiteTile;
+  static __device__ __forceinline__ void load_half(const char* base, const FieldDesc& f, int cb, int s, int h, R v[12]) {
+    const double2* p = reinterpret_cast<const double2*>(base) + tile_index(cb, s, 6 * h, f.L5, 12);
 #pragma unroll
     for (int g = 0; g < 6; ++g) {
       const v2d d = ldg<v2d>(p + (size_t)g * kSiteTile);
@@ -292,28 +267,18 @@ template <> struct SpinorIO<F64> {
       v[2 * g + 1] = d.y;
     }
   }
-  static __device__ __forceinline__ void store_at(char* base, const FieldDesc&, Loc l, const R v[24], bool nt = false) {
-    double2* p = at16<double2>(base, l.g);
-#pragma unroll
-    for (int g = 0; g < 12; ++g) stg<v2d>(p + (size_t)g * kSiteTile, v2d{v[2 * g], v[2 * g + 1]}, nt);
-  }
-  static __device__ __forceinline__ void load(const char* base, const FieldDesc& f, int cb, int s, R v[24]) {
-    load_at(base, f, spinor_loc(cb, s, f.L5, G), v);
-  }
-  static __device__ __forceinline__ void load_half(const char* base, const FieldDesc& f, int cb, int s, int h, R v[12]) {
-    load_half_at(base, f, spinor_loc(cb, s, f.L5, G), h, v);
-  }
   static __device__ __forceinline__ void store(char* base, const FieldDesc& f, int cb, int s, const R v[24],
                                                 bool nt = false) {
-    store_at(base, f, spinor_loc(cb, s, f.L5, G), v, nt);
+    double2* p = reinterpret_cast<double2*>(base) + tile_index(cb, s, 0, f.L5, 12);
+#pragma unroll
+    for (int g = 0; g < 12; ++g) stg<v2d>(p + (size_t)g * kSiteTile, v2d{v[2 * g], v[2 * g + 1]}, nt);
   }
 };
 
 template <> struct SpinorIO<F32> {
   using R = float;
-  static constexpr int G = 6;
-  static __device__ __forceinline__ void load_at(const char* base, const FieldDesc&, Loc l, R v[24]) {
-    const float4* p = at16<float4>(base, l.g);
+  static __device__ __forceinline__ void load(const char* base, const FieldDesc& f, int cb, int s, R v[24]) {
+    const float4* p = reinterpret_cast<const float4*>(base) + tile_index(cb, s, 0, f.L5, 6);
 #pragma unroll
     for (int g = 0; g < 6; ++g) {
       const v4f d = ldg<v4f>(p + (size_t)g * kSiteTile);
@@ -323,8 +288,8 @@ template <> struct SpinorIO<F32> {
       v[4 * g + 3] = d.w;
     }
   }
-  static __device__ __forceinline__ void load_half_at(const char* base, const FieldDesc&, Loc l, int h, R v[12]) {
-    const float4* p = at16<float4>(base, l.g) + (size_t)(3 * h) * kSiteTile;
+  static __device__ __forceinline__ void load_half(const char* base, const FieldDesc& f, int cb, int s, int h, R v[12]) {
+    const float4* p = reinterpret_cast<const float4*>(base) + tile_index(cb, s, 3 * h, f.L5, 6);
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
       const v4f d = ldg<v4f>(p + (size_t)g * kSiteTile);
@@ -334,21 +299,11 @@ template <> struct SpinorIO<F32> {
       v[4 * g + 3] = d.w;
     }
   }
-  static __device__ __forceinline__ void store_at(char* base, const FieldDesc&, Loc l, const R v[24], bool nt = false) {
-    float4* p = at16<float4>(base, l.g);
-#pragma unroll
-    for (int g = 0; g < 6; ++g)
-      stg<v4f>(p + (size_t)g * kSiteTile, v4f{v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]}, nt);
-  }
-  static __device__ __forceinline__ void load(const char* base, const FieldDesc& f, int cb, int s, R v[24]) {
-    load_at(base, f, spinor_loc(cb, s, f.L5, G), v);
-  }
-  static __device__ __forceinline__ void load_half(const char* base, const FieldDesc& f, int cb, int s, int h, R v[12]) {
-    load_half_at(base, f, spinor_loc(cb, s, f.L5, G), h, v);
-  }
   static __device__ __forceinline__ void store(char* base, const FieldDesc& f, int cb, int s, const R v[24],
                                                 bool nt = false) {
-    store_at(base, f, spinor_loc(cb, s, f.L5, G), v, nt);
+    float4* p = reinterpret_cast<float4*>(base) + tile_index(cb, s, 0, f.L5, 6);
+#pragma unroll
+    for (int g = 0; g < 6; ++g) stg<v4f>(p + (size_t)g * kSiteTile, v4f{v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]}, nt);
   }
 };
 
@@ -356,19 +311,11 @@ constexpr float kMinNormalF32 = 1.17549435e-38f;
 
 template <int P> struct SpinorIO16 {
   using R = float;
-  static constexpr int G = 3;
-  static __device__ __forceinline__ const float* scales(const char* base, const FieldDesc& f) {
-    return reinterpret_cast<const float*>(base + half_scale_offset(f.L5, f.Vh));
-  }
-  static __device__ __forceinline__ float scale_at(const char* base, const FieldDesc& f, Loc l) {
-    return ldg<float>(scales(base, f) + l.s);
-  }
   static __device__ __forceinline__ float scale(const char* base, const FieldDesc& f, int cb, int s) {
-    return scale_at(base, f, spinor_loc(cb, s, f.L5, G));
+    return ldg<float>(reinterpret_cast<const float*>(base + half_scale_offset(f.L5, f.Vh)) + tile_scale_index(cb, s, f.L5));
   }
-  // the 8 values of group g (v = stored value * sc)
-  static __device__ __forceinline__ void group_at(const char* base, Loc l, int g, float sc, R* v) {
-    const v4u q = ldg<v4u>(at16<uint4>(base, l.g) + (size_t)g * kSiteTile);
+  static __device__ __forceinline__ void group(const char* base, const FieldDesc& f, int cb, int s, int g, float sc, R* v) {
+    const v4u q = ldg<v4u>(reinterpret_cast<const uint4*>(base) + tile_index(cb, s, g, f.L5, 3));
     const uint32_t w[4] = {q.x, q.y, q.z, q.w};
     if constexpr (P == I16) {
       // q/32767 * sc as q * (sc/32767): one multiply per value
@@ -385,41 +332,30 @@ template <int P> struct SpinorIO16 {
       for (int k = 0; k < 8; ++k) v[k] *= sc;
     }
   }
-  static __device__ __forceinline__ void group(const char* base, const FieldDesc& f, int cb, int s, int g, float sc, R* v) {
-    group_at(base, spinor_loc(cb, s, f.L5, G), g, sc, v);
-  }
-  static __device__ __forceinline__ void load_at(const char* base, const FieldDesc& f, Loc l, R v[24]) {
-    const float sc = scale_at(base, f, l);
-#pragma unroll
-    for (int g = 0; g < 3; ++g) group_at(base, l, g, sc, v + 8 * g);
-  }
   static __device__ __forceinline__ void load(const char* base, const FieldDesc& f, int cb, int s, R v[24]) {
-    load_at(base, f, spinor_loc(cb, s, f.L5, G), v);
+    const float sc = scale(base, f, cb, s);
+#pragma unroll
+    for (int g = 0; g < 3; ++g) group(base, f, cb, s, g, sc, v + 8 * g);
   }
   // the 12 stored complex numbers as (re, im) 16-bit pairs, and the site's scale
-  static __device__ __forceinline__ void load_packed_at(const char* base, const FieldDesc& f, Loc l, uint32_t q[12],
-                                                        float& sc) {
-    sc = scale_at(base, f, l);
-    const uint4* p = at16<uint4>(base, l.g);
+  static __device__ __forceinline__ void load_packed(const char* base, const FieldDesc& f, int cb, int s, uint32_t q[12],
+                                                     float& sc) {
+    sc = scale(base, f, cb, s);
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
-      const v4u d = ldg<v4u>(p + (size_t)g * kSiteTile);
+      const v4u d = ldg<v4u>(reinterpret_cast<const uint4*>(base) + tile_index(cb, s, g, f.L5, 3));
       q[4 * g] = d.x;
       q[4 * g + 1] = d.y;
       q[4 * g + 2] = d.z;
       q[4 * g + 3] = d.w;
     }
   }
-  static __device__ __forceinline__ void load_packed(const char* base, const FieldDesc& f, int cb, int s, uint32_t q[12],
-                                                     float& sc) {
-    load_packed_at(base, f, spinor_loc(cb, s, f.L5, G), q, sc);
-  }
-  static __device__ __forceinline__ void load_half_at(const char* base, const FieldDesc& f, Loc l, int h, R v[12]) {
-    const float sc = scale_at(base, f, l);
+  static __device__ __forceinline__ void load_half(const char* base, const FieldDesc& f, int cb, int s, int h, R v[12]) {
+    const float sc = scale(base, f, cb, s);
     R t[16];
     // reals 0..11 live in groups 0 and 1 (first half), reals 12..23 in group 1 (second half) and 2
-    group_at(base, l, h, sc, t);
-    group_at(base, l, h + 1, sc, t + 8);
+    group(base, f, cb, s, h, sc, t);
+    group(base, f, cb, s, h + 1, sc, t + 8);
     if (h == 0) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) v[k] = t[k];
@@ -428,10 +364,8 @@ template <int P> struct SpinorIO16 {
       for (int k = 0; k < 12; ++k) v[k] = t[k + 4];
     }
   }
-  static __device__ __forceinline__ void load_half(const char* base, const FieldDesc& f, int cb, int s, int h, R v[12]) {
-    load_half_at(base, f, spinor_loc(cb, s, f.L5, G), h, v);
-  }
-  static __device__ __forceinline__ void store_at(char* base, const FieldDesc& f, Loc l, const R v[24], bool nt = false) {
+  static __device__ __forceinline__ void store(char* base, const FieldDesc& f, int cb, int s, const R v[24],
+                                                bool nt = false) {
     float m = 0.f;
 #pragma unroll
     for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf(v[k]));
@@ -440,7 +374,7 @@ template <int P> struct SpinorIO16 {
     const bool keep = m >= kMinNormalF32;
     const float inv = keep ? 1.0f / m : 0.f;
     if (!keep) m = 0.f;
-    uint4* p = at16<uint4>(base, l.g);
+    uint4* p = reinterpret_cast<uint4*>(base) + tile_index(cb, s, 0, f.L5, 3);
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
       const R* w = v + 8 * g;
@@ -448,11 +382,7 @@ template <int P> struct SpinorIO16 {
                   pack2<P>(w[4] * inv, w[5] * inv), pack2<P>(w[6] * inv, w[7] * inv)};
       stg<v4u>(p + (size_t)g * kSiteTile, q, nt);
     }
-    stg<float>(reinterpret_cast<float*>(base + half_scale_offset(f.L5, f.Vh)) + l.s, m, nt);
-  }
-  static __device__ __forceinline__ void store(char* base, const FieldDesc& f, int cb, int s, const R v[24],
-                                                bool nt = false) {
-    store_at(base, f, spinor_loc(cb, s, f.L5, G), v, nt);
+    stg<float>(reinterpret_cast<float*>(base + half_scale_offset(f.L5, f.Vh)) + tile_scale_index(cb, s, f.L5), m, nt);
   }
 };
 template <> struct SpinorIO<F16> : SpinorIO16<F16> {};

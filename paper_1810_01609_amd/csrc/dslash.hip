@@ -22,7 +22,7 @@ namespace mdwf {
 // One LDS row per site, so a thread's reads are its row base plus immediate
 // offsets; odd row strides keep consecutive sites on distinct banks.
 constexpr int kStageLinkStride = 8 * 18 + 1;  // link reals per site row
-constexpr int kStageNbrStride = 17;           // neighbour locations (2 words each) per site row
+constexpr int kStageNbrStride = 9;            // neighbour indices per site row
 
 // ---------------------------------------------------------------------------
 // spin projection.  h = spins 0,1 of (1 + SIG g_mu) psi; with w = U h the
@@ -220,15 +220,13 @@ __device__ __forceinline__ void colour_mul_packed(const uint32_t* lnk, int dir, 
 // a*x_s + b*(P5 x)_s (dag = 0) or a*x_s + b*(P5^T x)_s (dag = 1), loaded from
 // one site's fifth-dimension column.  P5: spins 0,1 from s-1, spins 2,3 from
 // s+1; P5^T the other way round; the wall hop carries -mq.
-// l0: the site's location on slice 0
 template <int P>
-__device__ __forceinline__ void load_bidiag_at(const char* base, const FieldDesc& f, Loc l0, int s, int L5,
-                                               typename PrecTraits<P>::Real a, typename PrecTraits<P>::Real b,
-                                               typename PrecTraits<P>::Real mq, bool dag,
-                                               typename PrecTraits<P>::Real v[24]) {
+__device__ __forceinline__ void load_bidiag(const char* base, const FieldDesc& f, int cb, int s, int L5,
+                                   typename PrecTraits<P>::Real a, typename PrecTraits<P>::Real b,
+                                   typename PrecTraits<P>::Real mq, bool dag,
+                                   typename PrecTraits<P>::Real v[24]) {
   using R = typename PrecTraits<P>::Real;
-  constexpr int G = SpinorIO<P>::G;
-  SpinorIO<P>::load_at(base, f, loc_slice(l0, s, G), v);
+  SpinorIO<P>::load(base, f, cb, s, v);
   int s_up = dag ? s + 1 : s - 1;  // source slice of spins 0,1
   int s_dn = dag ? s - 1 : s + 1;  // source slice of spins 2,3
   R b_up = b, b_dn = b;
@@ -237,21 +235,13 @@ __device__ __forceinline__ void load_bidiag_at(const char* base, const FieldDesc
   if (s_dn < 0) { s_dn = L5 - 1; b_dn = -b * mq; }
   if (s_dn >= L5) { s_dn = 0; b_dn = -b * mq; }
   R u[12], d[12];
-  SpinorIO<P>::load_half_at(base, f, loc_slice(l0, s_up, G), 0, u);
-  SpinorIO<P>::load_half_at(base, f, loc_slice(l0, s_dn, G), 1, d);
+  SpinorIO<P>::load_half(base, f, cb, s_up, 0, u);
+  SpinorIO<P>::load_half(base, f, cb, s_dn, 1, d);
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     v[k] = a * v[k] + b_up * u[k];
     v[12 + k] = a * v[12 + k] + b_dn * d[k];
   }
-}
-
-template <int P>
-__device__ __forceinline__ void load_bidiag(const char* base, const FieldDesc& f, int cb, int s, int L5,
-                                            typename PrecTraits<P>::Real a, typename PrecTraits<P>::Real b,
-                                            typename PrecTraits<P>::Real mq, bool dag,
-                                            typename PrecTraits<P>::Real v[24]) {
-  load_bidiag_at<P>(base, f, spinor_loc(cb, 0, L5, SpinorIO<P>::G), s, L5, a, b, mq, dag, v);
 }
 
 // Compiler fence that also pins the accumulator: the arithmetic of one
@@ -267,13 +257,12 @@ __device__ __forceinline__ void pin_acc(Cplx<R> acc[4][3]) {
 
 // Per-workgroup staging of the stencil's geometry and links in LDS: for each
 // of the CB sites and 8 directions (mu forward 0..3, backward 4..7) the
-// neighbour's location on slice 0 (so a slice thread forms its load address
-// with one add) and the full 3x3 link (row 2 rebuilt once here instead of
+// neighbour's index and the full 3x3 link (row 2 rebuilt once here instead of
 // once per slice thread), loaded once and shared by the site's L5 slice
 // threads.  A hop across the antiperiodic t boundary carries its -1 in the
 // staged link: U(-h) and (-U)h round identically.
 template <class R> struct Stage {
-  uint32_t* nbr;  // [CB][17]: 2 * dir + (0: group index | 1: scale index) of the neighbour on slice 0
+  int* nbr;  // [CB][9]: dir
   R* lnk;    // [CB][145]: dir * 18 + 2 * (3a + b) + (re | im)
 };
 
@@ -283,17 +272,13 @@ __device__ __forceinline__ void stage_link(const Stage<R>& st, int dir, int CB, 
 #pragma unroll
   for (int k = 0; k < 9; ++k) U[k / 3][k % 3] = {row[2 * k], row[2 * k + 1]};
 }
-constexpr uint32_t kNoNbr = 0xffffffffu;
-__device__ __forceinline__ Loc stage_nbr(const uint32_t* nbr, int dir, int cbl) {
-  const uint32_t* q = nbr + cbl * kStageNbrStride + 2 * dir;
-  return Loc{q[0], q[1]};
-}
+__device__ __forceinline__ int stage_nbr(const int* nbr, int dir, int cbl) { return nbr[cbl * kStageNbrStride + dir]; }
 __host__ __device__ __forceinline__ size_t stage_nbr_bytes(int CB) {
-  return round_up((size_t)CB * kStageNbrStride * sizeof(uint32_t), 16);
+  return round_up((size_t)CB * kStageNbrStride * sizeof(int), 16);
 }
 
 // SPLIT: a hop across the boundary of a split dimension is staged with
-// the location kNoNbr (and a zero link); the hop skips it.
+// neighbour index -1 (and a zero link); the hop skips it.
 template <int P, bool SPLIT>
 __device__ __forceinline__ void stage_fill(const DslashArgs& A, Stage<typename PrecTraits<P>::Real> st, int CB,
                                            int cb_log2, int cb0, int tid, int nthr) {
@@ -331,9 +316,7 @@ __device__ __forceinline__ void stage_fill(const DslashArgs& A, Stage<typename P
     Cplx<R> U[3][3];
     link_from_raw(r, U);
     const R sg = flip ? R(-1) : R(1);
-    const Loc l = nb < 0 ? Loc{kNoNbr, kNoNbr} : spinor_loc(nb, 0, g.L5, SpinorIO<P>::G);
-    st.nbr[cbl * kStageNbrStride + 2 * dir] = l.g;
-    st.nbr[cbl * kStageNbrStride + 2 * dir + 1] = l.s;
+    st.nbr[cbl * kStageNbrStride + dir] = nb;
     R* row = st.lnk + cbl * kStageLinkStride + dir * 18;
     if constexpr (Packed<P>::enabled) {
       // V = U or U^dag as the pairs (Re V, -Im V), (Im V, Re V)
@@ -361,26 +344,25 @@ __device__ __forceinline__ void stage_fill(const DslashArgs& A, Stage<typename P
 // divided by their maximum m, which is returned: the combination stays O(1)
 // whatever the field's magnitude, so it can be rounded back to 16 bits.
 template <int P>
-__device__ __forceinline__ float load_bidiag_norm(const char* base, const FieldDesc& f, Loc l0, int s, int L5, float a,
+__device__ __forceinline__ float load_bidiag_norm(const char* base, const FieldDesc& f, int cb, int s, int L5, float a,
                                                   float b, float mq, float v[24]) {
   int s_up = s - 1, s_dn = s + 1;
   float b_up = b, b_dn = b;
   if (s_up < 0) { s_up = L5 - 1; b_up = -b * mq; }
   if (s_dn >= L5) { s_dn = 0; b_dn = -b * mq; }
   using IO = SpinorIO<P>;
-  const Loc lc = loc_slice(l0, s, 3), lu = loc_slice(l0, s_up, 3), ld = loc_slice(l0, s_dn, 3);
-  const float c0 = IO::scale_at(base, f, lc), cu = IO::scale_at(base, f, lu), cd = IO::scale_at(base, f, ld);
+  const float c0 = IO::scale(base, f, cb, s), cu = IO::scale(base, f, cb, s_up), cd = IO::scale(base, f, cb, s_dn);
   const float m = fmaxf(c0, fmaxf(cu, cd));
   const float im = m >= kMinNormalF32 ? 1.0f / m : 0.f;  // stored scales are 0 or normal
 #pragma unroll
-  for (int g = 0; g < 3; ++g) IO::group_at(base, lc, g, a * c0 * im, v + 8 * g);
+  for (int g = 0; g < 3; ++g) IO::group(base, f, cb, s, g, a * c0 * im, v + 8 * g);
   float t[16];
-  IO::group_at(base, lu, 0, b_up * cu * im, t);
-  IO::group_at(base, lu, 1, b_up * cu * im, t + 8);
+  IO::group(base, f, cb, s_up, 0, b_up * cu * im, t);
+  IO::group(base, f, cb, s_up, 1, b_up * cu * im, t + 8);
 #pragma unroll
   for (int k = 0; k < 12; ++k) v[k] += t[k];
-  IO::group_at(base, ld, 1, b_dn * cd * im, t);
-  IO::group_at(base, ld, 2, b_dn * cd * im, t + 8);
+  IO::group(base, f, cb, s_dn, 1, b_dn * cd * im, t);
+  IO::group(base, f, cb, s_dn, 2, b_dn * cd * im, t + 8);
 #pragma unroll
   for (int k = 0; k < 12; ++k) v[12 + k] += t[4 + k];
   return m;
@@ -397,15 +379,15 @@ __device__ __forceinline__ void hop_dir_packed(const DslashArgs& A, const FieldD
   const uint32_t* lnk = reinterpret_cast<const uint32_t*>(st.lnk);
 #pragma unroll
   for (int fb = 0; fb < 2; ++fb) {
-    const Loc l0 = stage_nbr(st.nbr, MU + 4 * fb, cbl);
+    const int nb = stage_nbr(st.nbr, MU + 4 * fb, cbl);
     if constexpr (SPLIT) {
-      if (l0.g == kNoNbr) continue;
+      if (nb < 0) continue;
     }
     T2 h[2][3];
     float sc;
     if constexpr (PRO) {
       float v[24];
-      sc = load_bidiag_norm<P>(in, f, l0, s, A.g.L5, (float)c.b5, (float)c.c5, (float)c.mq, v);
+      sc = load_bidiag_norm<P>(in, f, nb, s, A.g.L5, (float)c.b5, (float)c.c5, (float)c.mq, v);
       Cplx<float> pf[4][3], hf[2][3];
 #pragma unroll
       for (int k = 0; k < 12; ++k) pf[k / 3][k % 3] = {v[2 * k], v[2 * k + 1]};
@@ -417,7 +399,7 @@ __device__ __forceinline__ void hop_dir_packed(const DslashArgs& A, const FieldD
         for (int a = 0; a < 3; ++a) h[k][a] = K::make(hf[k][a].re, hf[k][a].im);
     } else {
       uint32_t q[12];
-      SpinorIO<P>::load_packed_at(in, f, loc_slice(l0, s, 3), q, sc);
+      SpinorIO<P>::load_packed(in, f, nb, s, q, sc);
       T2 psi[4][3];
 #pragma unroll
       for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = __builtin_bit_cast(T2, q[k]);
@@ -443,16 +425,15 @@ __device__ __forceinline__ void hop_dir_single(const DslashArgs& A, const FieldD
   constexpr int SB = -SF;            // backward projector
   Cplx<R> U[3][3], psi[4][3], h[2][3], w[2][3];
   R v[24];
-  constexpr int G = SpinorIO<P>::G;
 #pragma unroll
   for (int fb = 0; fb < 2; ++fb) {
     // fb = 0 forward: (1 -+ g) U_mu(x) psi(x + mu); fb = 1 backward: (1 +- g) U_mu(x - mu)^dag psi(x - mu)
-    Loc l0;  // the neighbour on slice 0
+    int nb;
     bool flip;
     if constexpr (STAGE) {
-      l0 = stage_nbr(st.nbr, MU + 4 * fb, cbl);
+      nb = stage_nbr(st.nbr, MU + 4 * fb, cbl);
       if constexpr (SPLIT) {
-        if (l0.g == kNoNbr) continue;
+        if (nb < 0) continue;
       }
       flip = false;  // carried by the staged link
       stage_link(st, MU + 4 * fb, CB, cbl, U);
@@ -465,8 +446,7 @@ __device__ __forceinline__ void hop_dir_single(const DslashArgs& A, const FieldD
         Y[MU] = X[MU] == 0 ? Lmu - 1 : X[MU] - 1;
         flip = MU == 3 && g.tap && X[3] == 0;
       }
-      const int nb = cb_index(g, Y[0], Y[1], Y[2], Y[3]);
-      l0 = spinor_loc(nb, 0, g.L5, G);
+      nb = cb_index(g, Y[0], Y[1], Y[2], Y[3]);
       if (fb == 0) LinkIO<P>::load(A.gauge, g.Vh, A.out_par, MU, cb, U);
       else LinkIO<P>::load(A.gauge, g.Vh, 1 - A.out_par, MU, nb, U);
     }
@@ -478,14 +458,14 @@ __device__ __forceinline__ void hop_dir_single(const DslashArgs& A, const FieldD
     float sc16 = 1.f;
     if constexpr (kI16Raw) {
       uint32_t q[12];
-      SpinorIO<P>::load_packed_at(in, f, loc_slice(l0, s, G), q, sc16);
+      SpinorIO<P>::load_packed(in, f, nb, s, q, sc16);
       sc16 *= 1.0f / 32767.0f;
 #pragma unroll
       for (int k = 0; k < 12; ++k)
         psi[k / 3][k % 3] = {(R)(int16_t)(uint16_t)(q[k] & 0xffffu), (R)(int16_t)(uint16_t)(q[k] >> 16)};
     } else {
-      if constexpr (PRO) load_bidiag_at<P>(in, f, l0, s, g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v);
-      else SpinorIO<P>::load_at(in, f, loc_slice(l0, s, G), v);
+      if constexpr (PRO) load_bidiag<P>(in, f, nb, s, g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, v);
+      else SpinorIO<P>::load(in, f, nb, s, v);
 #pragma unroll
       for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = {v[2 * k], v[2 * k + 1]};
     }
@@ -516,41 +496,51 @@ __device__ __forceinline__ void hop_dir_single(const DslashArgs& A, const FieldD
 // the eight directions (mu-major, forward then backward, the order of the
 // one-at-a-time form, so the sums round identically) are taken in batches of
 // NB; a batch first loads its NB neighbours (NB loads in flight per thread),
-// then projects, multiplies and accumulates them one by one.
+// then projects, multiplies and accumulates them one by one.  Used for the
+// staged hop without the M_phi prologue.
 // ---------------------------------------------------------------------------
-template <int P, bool PRO> struct NbrLoad {
+template <int P> struct NbrLoad {
   using R = typename PrecTraits<P>::Real;
-  // 16-bit storage without a prologue keeps the stored pairs and the scale
-  static constexpr bool kRaw = (Packed<P>::enabled || P == I16) && !PRO;
+  // 16-bit storage keeps the stored pairs and the scale
+  static constexpr bool kRaw = Packed<P>::enabled || P == I16;
   uint32_t q[kRaw ? 12 : 1];
   R v[kRaw ? 1 : 24];
   float sc;
   bool skip;
 };
 
-template <int P, bool PRO, bool SPLIT, int D>
-__device__ __forceinline__ void nbr_load(const DslashArgs& A, const FieldDesc& f, const char* in, int s,
-                                         const Coef5& c, const uint32_t* nbr, int cbl, NbrLoad<P, PRO>& n) {
-  constexpr int MU = D / 2, FB = D % 2, G = SpinorIO<P>::G;
-  const Loc l0 = stage_nbr(nbr, MU + 4 * FB, cbl);
-  n.skip = SPLIT && l0.g == kNoNbr;
+template <int P, bool SPLIT, int D>
+__device__ __forceinline__ void nbr_load(const FieldDesc& f, const char* in, int s, const int* nbr, int cbl,
+                                         NbrLoad<P>& n) {
+  constexpr int MU = D / 2, FB = D % 2;
+  const int nb = stage_nbr(nbr, MU + 4 * FB, cbl);
+  n.skip = SPLIT && nb < 0;
   n.sc = 1.f;
   if (n.skip) return;
-  if constexpr (NbrLoad<P, PRO>::kRaw) {
-    SpinorIO<P>::load_packed_at(in, f, loc_slice(l0, s, G), n.q, n.sc);
-  } else if constexpr (PRO && Packed<P>::enabled) {
-    n.sc = load_bidiag_norm<P>(in, f, l0, s, A.g.L5, (float)c.b5, (float)c.c5, (float)c.mq, n.v);
-  } else if constexpr (PRO) {
-    using R = typename PrecTraits<P>::Real;
-    load_bidiag_at<P>(in, f, l0, s, A.g.L5, (R)c.b5, (R)c.c5, (R)c.mq, false, n.v);
-  } else {
-    SpinorIO<P>::load_at(in, f, loc_slice(l0, s, G), n.v);
-  }
+  if constexpr (NbrLoad<P>::kRaw) SpinorIO<P>::load_packed(in, f, nb, s, n.q, n.sc);
+  else SpinorIO<P>::load(in, f, nb, s, n.v);
 }
 
-template <int P, bool DAG, bool PRO, int D>
+// Compiler fence after a batch's loads: every loaded register passes through
+// an empty asm, so no load of the batch can sink below it and no arithmetic
+// of the batch can rise above it.
+template <class T, int N> __device__ __forceinline__ void pin_regs(T (&v)[N]) {
+#pragma unroll
+  for (int k = 0; k + 3 < N; k += 4) asm volatile("" : "+v"(v[k]), "+v"(v[k + 1]), "+v"(v[k + 2]), "+v"(v[k + 3]) : : "memory");
+  if constexpr (N % 4 != 0) {
+#pragma unroll
+    for (int k = N - N % 4; k < N; ++k) asm volatile("" : "+v"(v[k]) : : "memory");
+  }
+}
+template <int P> __device__ __forceinline__ void pin_load(NbrLoad<P>& n) {
+  if constexpr (NbrLoad<P>::kRaw) pin_regs(n.q);
+  else pin_regs(n.v);
+  asm volatile("" : "+v"(n.sc) : : "memory");
+}
+
+template <int P, bool DAG, int D>
 __device__ __forceinline__ void nbr_compute(const Stage<typename PrecTraits<P>::Real>& st, int CB, int cbl,
-                                            const NbrLoad<P, PRO>& n, Cplx<typename PrecTraits<P>::Real> acc[4][3]) {
+                                            const NbrLoad<P>& n, Cplx<typename PrecTraits<P>::Real> acc[4][3]) {
   using R = typename PrecTraits<P>::Real;
   constexpr int MU = D / 2, FB = D % 2;
   constexpr int SG = (FB == 0) == DAG ? +1 : -1;  // projector 1 + SG g_mu
@@ -558,29 +548,17 @@ __device__ __forceinline__ void nbr_compute(const Stage<typename PrecTraits<P>::
   if constexpr (Packed<P>::enabled) {
     using K = Packed<P>;
     using T2 = typename K::T2;
-    T2 h[2][3];
-    if constexpr (PRO) {
-      Cplx<float> pf[4][3], hf[2][3];
+    T2 psi[4][3], h[2][3];
 #pragma unroll
-      for (int k = 0; k < 12; ++k) pf[k / 3][k % 3] = {n.v[2 * k], n.v[2 * k + 1]};
-      project<MU, SG>(pf, hf);
-#pragma unroll
-      for (int k = 0; k < 2; ++k)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) h[k][a] = K::make(hf[k][a].re, hf[k][a].im);
-    } else {
-      T2 psi[4][3];
-#pragma unroll
-      for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = __builtin_bit_cast(T2, n.q[k]);
-      project<MU, SG>(psi, h);
-    }
+    for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = __builtin_bit_cast(T2, n.q[k]);
+    project<MU, SG>(psi, h);
     Cplx<float> w[2][3];
     colour_mul_packed<P>(reinterpret_cast<const uint32_t*>(st.lnk), MU + 4 * FB, CB, cbl, h, w);
     accumulate_scaled<MU, SG>(acc, w, n.sc);
   } else {
     Cplx<R> U[3][3], psi[4][3], h[2][3], w[2][3];
     stage_link(st, MU + 4 * FB, CB, cbl, U);
-    if constexpr (NbrLoad<P, PRO>::kRaw) {  // int16: unscaled integers, the scale joins the accumulation
+    if constexpr (NbrLoad<P>::kRaw) {  // int16: unscaled integers, the scale joins the accumulation
 #pragma unroll
       for (int k = 0; k < 12; ++k)
         psi[k / 3][k % 3] = {(R)(int16_t)(uint16_t)(n.q[k] & 0xffffu), (R)(int16_t)(uint16_t)(n.q[k] >> 16)};
@@ -590,72 +568,55 @@ __device__ __forceinline__ void nbr_compute(const Stage<typename PrecTraits<P>::
     }
     project<MU, SG>(psi, h);
     colour_mul<FB == 1>(U, h, w);
-    if constexpr (NbrLoad<P, PRO>::kRaw) accumulate_scaled<MU, SG>(acc, w, n.sc * (1.0f / 32767.0f));
+    if constexpr (NbrLoad<P>::kRaw) accumulate_scaled<MU, SG>(acc, w, n.sc * (1.0f / 32767.0f));
     else accumulate<MU, SG>(acc, w);
   }
 }
 
-// Compiler fence after a batch's loads: every loaded register passes through
-// an empty asm, so no load of the batch can sink below it (below the first
-// use) and no arithmetic of the batch can rise above it.
-template <class T, int N> __device__ __forceinline__ void pin_regs(T (&v)[N]) {
-#pragma unroll
-  for (int k = 0; k + 3 < N; k += 4) asm volatile("" : "+v"(v[k]), "+v"(v[k + 1]), "+v"(v[k + 2]), "+v"(v[k + 3]) : : "memory");
-  if constexpr (N % 4 != 0) {
-#pragma unroll
-    for (int k = N - N % 4; k < N; ++k) asm volatile("" : "+v"(v[k]) : : "memory");
-  }
-}
-template <int P, bool PRO> __device__ __forceinline__ void pin_load(NbrLoad<P, PRO>& n) {
-  if constexpr (NbrLoad<P, PRO>::kRaw) pin_regs(n.q);
-  else pin_regs(n.v);
-  asm volatile("" : "+v"(n.sc) : : "memory");
-}
-
-template <int P, bool DAG, bool PRO, bool SPLIT, int D, int END> struct HopBatch {
-  static __device__ __forceinline__ void load(const DslashArgs& A, const FieldDesc& f, const char* in, int s,
-                                              const Coef5& c, const uint32_t* nbr, int cbl, NbrLoad<P, PRO>* n) {
+template <int P, bool DAG, bool SPLIT, int D, int END> struct HopBatch {
+  static __device__ __forceinline__ void load(const FieldDesc& f, const char* in, int s, const int* nbr, int cbl,
+                                              NbrLoad<P>* n) {
     if constexpr (D < END) {
-      nbr_load<P, PRO, SPLIT, D>(A, f, in, s, c, nbr, cbl, n[0]);
-      HopBatch<P, DAG, PRO, SPLIT, D + 1, END>::load(A, f, in, s, c, nbr, cbl, n + 1);
+      nbr_load<P, SPLIT, D>(f, in, s, nbr, cbl, n[0]);
+      HopBatch<P, DAG, SPLIT, D + 1, END>::load(f, in, s, nbr, cbl, n + 1);
     }
   }
   static __device__ __forceinline__ void compute(const Stage<typename PrecTraits<P>::Real>& st, int CB, int cbl,
-                                                 const NbrLoad<P, PRO>* n, Cplx<typename PrecTraits<P>::Real> acc[4][3]) {
+                                                 const NbrLoad<P>* n, Cplx<typename PrecTraits<P>::Real> acc[4][3]) {
     if constexpr (D < END) {
-      nbr_compute<P, DAG, PRO, D>(st, CB, cbl, n[0], acc);
-      HopBatch<P, DAG, PRO, SPLIT, D + 1, END>::compute(st, CB, cbl, n + 1, acc);
+      nbr_compute<P, DAG, D>(st, CB, cbl, n[0], acc);
+      HopBatch<P, DAG, SPLIT, D + 1, END>::compute(st, CB, cbl, n + 1, acc);
     }
   }
 };
 
-template <int P, bool DAG, bool PRO, bool SPLIT, int NB, int B0>
-__device__ __forceinline__ void hop_batches(const DslashArgs& A, const FieldDesc& f, const char* in, int s,
-                                            const Coef5& c, Cplx<typename PrecTraits<P>::Real> acc[4][3],
+template <int P, bool DAG, bool SPLIT, int NB, int B0>
+__device__ __forceinline__ void hop_batches(const FieldDesc& f, const char* in, int s,
+                                            Cplx<typename PrecTraits<P>::Real> acc[4][3],
                                             const Stage<typename PrecTraits<P>::Real>& st, int CB, int cbl) {
   if constexpr (B0 < 8) {
-    NbrLoad<P, PRO> n[NB];
-    HopBatch<P, DAG, PRO, SPLIT, B0, B0 + NB>::load(A, f, in, s, c, st.nbr, cbl, n);
-    if constexpr (NB > 1) {
+    NbrLoad<P> n[NB];
+    HopBatch<P, DAG, SPLIT, B0, B0 + NB>::load(f, in, s, st.nbr, cbl, n);
 #pragma unroll
-      for (int j = 0; j < NB; ++j) pin_load(n[j]);
-    }
-    HopBatch<P, DAG, PRO, SPLIT, B0, B0 + NB>::compute(st, CB, cbl, n, acc);
+    for (int j = 0; j < NB; ++j) pin_load(n[j]);
+    HopBatch<P, DAG, SPLIT, B0, B0 + NB>::compute(st, CB, cbl, n, acc);
     pin_acc(acc);
-    hop_batches<P, DAG, PRO, SPLIT, NB, B0 + NB>(A, f, in, s, c, acc, st, CB, cbl);
+    hop_batches<P, DAG, SPLIT, NB, B0 + NB>(f, in, s, acc, st, CB, cbl);
   }
 }
 
-// Neighbours loaded together per thread (0: the one-at-a-time form).  Two
-// at a time, measured on 32^3 x 64 x 12 against one: the plain hop +3 % (FP32,
-// FP16, BF16) and +7 % (int16), M^+ +1-4 %; four and eight lower the
-// occupancy more than they gain.  The kernels with the M_phi prologue load
-// three slices per neighbour and stay at one (two spilled in 16 bits).  FP64
-// (reliable updates only) stays at one.
+// Neighbours loaded together per thread (0: the one-at-a-time form) in the
+// staged hop without the M_phi prologue; the build options MDWF_HOP_BATCH and
+// MDWF_HOP_BATCH_CGU (launches with the fused CG update) set it.  FP64 stays
+// at one.
 #ifndef MDWF_HOP_BATCH
 #define MDWF_HOP_BATCH 2
 #endif
-template <int P, bool PRO> constexpr int kHopBatch = (P == F64 || PRO) ? 0 : MDWF_HOP_BATCH;
+#ifndef MDWF_HOP_BATCH_CGU
+#define MDWF_HOP_BATCH_CGU 0
+#endif
+template <int P, bool PRO, bool CGU> constexpr int kHopBatch =
+    (P == F64 || PRO) ? 0 : CGU ? MDWF_HOP_BATCH_CGU : MDWF_HOP_BATCH;
 
 template <int P, bool DAG, bool PRO, bool STAGE, int MU, bool SPLIT>
 __device__ __forceinline__ void hop_dir(const DslashArgs& A, const FieldDesc& f, const char* in, int cb, int s,
@@ -745,22 +706,12 @@ template <class R> __device__ __forceinline__ void col_bidiag(const Column<R>& c
   col.set(0, {a * y.re - b * mq * last.re, a * y.im - b * mq * last.im});
 }
 
-// lds0: the chain columns of the workgroup's RHS 0 (those of RHS k follow at
-// k * CB * L5 * kChainStride); one task per (RHS, site, complex component),
-// each RHS with its own coefficients; absent RHS are skipped.
 template <class R>
-__device__ __forceinline__ void run_chain(R* lds0, int op, int CB, int cb_log2, int L5, const DslashArgs& A, int slot0,
-                                          int tid, int nthr) {
+__device__ __forceinline__ void run_chain(R* lds, int op, int CB, int cb_log2, int L5, const Coef5& c, int tid, int nthr) {
   const bool dag = op == CH_M5INV_DAG || op == CH_MPHI_DAG || op == CH_M5_DAG || op == CH_MPHIDAG_M5INVDAG;
-  const int per = CB * 12;
-  for (int task = tid; task < per * A.nrw; task += nthr) {
-    const int rr = task / per;
-    const int t = task - rr * per;
-    if (slot0 + rr >= A.nslots) break;
-    const Coef5 c = A.coef[slot0 + rr];
-    R* lds = lds0 + (size_t)rr * CB * L5 * kChainStride;
-    const int cbl = t & (CB - 1);
-    const int j = t >> cb_log2;
+  for (int task = tid; task < CB * 12; task += nthr) {
+    const int cbl = task & (CB - 1);
+    const int j = task >> cb_log2;
     const bool plus = j < 6;
     const int stride = kChainStride * CB;
     R* base = lds + cbl * kChainStride + 2 * j;
@@ -832,10 +783,7 @@ __device__ __forceinline__ int block_first_site(const DslashArgs& A, int q, int 
 
 // FP64 needs ~180 VGPRs per thread (2 waves per SIMD), the 32-bit
 // arithmetic variants fit 128 (4 waves per SIMD).
-#ifndef MDWF_MAX_THREADS_32
-#define MDWF_MAX_THREADS_32 1024
-#endif
-template <int P> constexpr int kMaxThreads = P == F64 ? 512 : MDWF_MAX_THREADS_32;
+template <int P> constexpr int kMaxThreads = P == F64 ? 512 : 1024;
 
 // Resident waves per SIMD the register allocation must leave room for.  The
 // 16-bit kernels are asked for 6 (67-80 VGPRs instead of 83-102, no spills in
@@ -846,12 +794,8 @@ template <int P> constexpr int kMaxThreads = P == F64 ? 512 : MDWF_MAX_THREADS_3
 #ifndef MDWF_WAVES_PER_EU
 #define MDWF_WAVES_PER_EU 0
 #endif
-#ifndef MDWF_WAVES_PER_EU_32
-#define MDWF_WAVES_PER_EU_32 0
-#endif
 template <int P> constexpr int kWavesPerEU =
-    (P == F16 || P == BF16 || P == I16) ? (MDWF_WAVES_PER_EU > 0 ? MDWF_WAVES_PER_EU : 6)
-    : (P == F32 && MDWF_WAVES_PER_EU_32 > 0) ? MDWF_WAVES_PER_EU_32 : kMaxThreads<P> / 256;
+    (P == F16 || P == BF16 || P == I16) ? (MDWF_WAVES_PER_EU > 0 ? MDWF_WAVES_PER_EU : 6) : kMaxThreads<P> / 256;
 
 template <int P, bool HOP, bool DAG, bool PRO, bool STAGE, bool CGU, bool SPLIT>
 __global__ __launch_bounds__(kMaxThreads<P>) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<P>))) void dslash5_kernel(
@@ -861,40 +805,20 @@ __global__ __launch_bounds__(kMaxThreads<P>) __attribute__((amdgpu_waves_per_eu(
   const int CB = 1 << A.cb_log2;
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
-  const int L5 = A.g.L5;
   const int cbl = tid & (CB - 1);
-  const int sr = tid >> A.cb_log2;  // s + L5 * (RHS within the workgroup)
-  // the launcher allows several RHS per workgroup only when CB * L5 is a
-  // multiple of 64: every wavefront then serves one RHS, and its slot,
-  // coefficients and field pointers stay in scalar registers
-  const int rr = __builtin_amdgcn_readfirstlane(sr / L5);
-  const int s = sr - rr * L5;
-  // a workgroup serves sites [cb0, cb0 + CB) of RHS group grp: slots
-  // grp * nrw ... grp * nrw + nrw - 1, which share the staged links
-  const int ngroups = (A.nslots + A.nrw - 1) / A.nrw;
+  const int s = tid >> A.cb_log2;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  if (lb >= ngroups * A.nblk) return;
-  const int grp = lb % ngroups;
-  const int slot0 = grp * A.nrw;
-  const int slot = slot0 + rr;
-  auto slot_live = [&](int sl) {
-    return sl < A.nslots && (A.active == nullptr || A.active[(size_t)sl * A.active_stride] != 0);
-  };
-  {
-    bool any = false;
-    for (int k = 0; k < A.nrw; ++k) any = any || slot_live(slot0 + k);
-    if (!any) return;  // every RHS of the group is frozen: the whole workgroup leaves
-  }
-  // a thread of a frozen (or absent) RHS does no loads or stores but takes
-  // part in the workgroup's barriers
-  const bool live = slot_live(slot);
-  const int cb0 = block_first_site(A, lb / ngroups, CB);
+  if (lb >= A.nslots * A.nblk) return;
+  const int slot = lb % A.nslots;
+  const int cb0 = block_first_site(A, lb / A.nslots, CB);
+  if (A.active != nullptr && A.active[(size_t)slot * A.active_stride] == 0) return;
   const int cb = cb0 + cbl;
-  const bool valid = live && cb < A.g.Vh;
-  const Coef5 c = A.coef[live ? slot : slot0];
+  const bool valid = cb < A.g.Vh;
+  const Coef5 c = A.coef[slot];
   const FieldDesc f{A.g.Vh, A.g.L5};
+  const int L5 = A.g.L5;
 
-  Stage<R> st{reinterpret_cast<uint32_t*>(smem + A.lds_stage_off),
+  Stage<R> st{reinterpret_cast<int*>(smem + A.lds_stage_off),
               reinterpret_cast<R*>(smem + A.lds_stage_off + stage_nbr_bytes(CB))};
   if constexpr (HOP && STAGE) {
     stage_fill<P, SPLIT>(A, st, CB, A.cb_log2, cb0, tid, nthr);
@@ -914,8 +838,8 @@ __global__ __launch_bounds__(kMaxThreads<P>) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (int b = 0; b < 3; ++b) acc[a][b] = {0, 0};
       const char* in = A.in[slot];
-      if constexpr (STAGE && kHopBatch<P, PRO> > 0) {
-        hop_batches<P, DAG, PRO, SPLIT, kHopBatch<P, PRO>, 0>(A, f, in, s, c, acc, st, CB, cbl);
+      if constexpr (STAGE && kHopBatch<P, PRO, CGU> > 0) {
+        hop_batches<P, DAG, SPLIT, kHopBatch<P, PRO, CGU>, 0>(f, in, s, acc, st, CB, cbl);
       } else {
         hop_dir<P, DAG, PRO, STAGE, 0, SPLIT>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
         hop_dir<P, DAG, PRO, STAGE, 1, SPLIT>(A, f, in, cb, s, X, c, acc, st, CB, cbl);
@@ -932,13 +856,12 @@ __global__ __launch_bounds__(kMaxThreads<P>) __attribute__((amdgpu_waves_per_eu(
     }
   }
 
-  R* const lds0 = reinterpret_cast<R*>(smem);
-  R* lds = lds0 + (size_t)rr * CB * L5 * kChainStride;  // this RHS's chain columns
+  R* lds = reinterpret_cast<R*>(smem);
   if (A.c1 != CH_NONE) {
     if constexpr (HOP && STAGE) __syncthreads();  // the chain columns overlay the stage
     lds_put(lds, CB, cbl, s, v);
     __syncthreads();
-    run_chain(lds0, A.c1, CB, A.cb_log2, L5, A, slot0, tid, nthr);
+    run_chain(lds, A.c1, CB, A.cb_log2, L5, c, tid, nthr);
     __syncthreads();
     lds_get(lds, CB, cbl, s, v);
   }
@@ -948,9 +871,8 @@ __global__ __launch_bounds__(kMaxThreads<P>) __attribute__((amdgpu_waves_per_eu(
   if (A.aux_mode != AUX_NONE && valid) {
     R w[24];
     const char* aux = A.aux[slot];
-    const Loc l0 = spinor_loc(cb, 0, L5, SpinorIO<P>::G);
-    if (A.aux_mode == AUX_PLAIN) SpinorIO<P>::load_at(aux, f, loc_slice(l0, s, SpinorIO<P>::G), w);
-    else load_bidiag_at<P>(aux, f, l0, s, L5, (R)c.alpha, (R)c.beta, (R)c.mq, A.aux_mode == AUX_M5DAG, w);
+    if (A.aux_mode == AUX_PLAIN) SpinorIO<P>::load(aux, f, cb, s, w);
+    else load_bidiag<P>(aux, f, cb, s, L5, (R)c.alpha, (R)c.beta, (R)c.mq, A.aux_mode == AUX_M5DAG, w);
 #pragma unroll
     for (int k = 0; k < 24; ++k) v[k] = cy * v[k] + w[k];
   } else if (A.coef_y != 1.0) {
@@ -987,7 +909,7 @@ __global__ __launch_bounds__(kMaxThreads<P>) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
     for (int k = 0; k < 24; ++k) lr += v[k] * v[k];
     const double loc = (double)lr;
-    double* red = reinterpret_cast<double*>(smem + A.lds_chain_bytes) + (size_t)rr * L5 * CB;
+    double* red = reinterpret_cast<double*>(smem + A.lds_chain_bytes);
     red[s * CB + cbl] = loc;
     __syncthreads();
     double site = 0;
@@ -996,7 +918,7 @@ __global__ __launch_bounds__(kMaxThreads<P>) __attribute__((amdgpu_waves_per_eu(
     // fixed 16-site tree (one DPP row = one 16-site tile): the same
     // summation order whatever CB is
     site = row_sum16(site);
-    if (live && s == 0 && (cbl & 15) == 0) {
+    if (s == 0 && (cbl & 15) == 0) {
       const int tile = cb >> 4;
       if (tile < A.ntiles) A.partials[(size_t)slot * A.ntiles + tile] = site;
     }
@@ -1006,7 +928,7 @@ __global__ __launch_bounds__(kMaxThreads<P>) __attribute__((amdgpu_waves_per_eu(
     __syncthreads();
     lds_put(lds, CB, cbl, s, v);
     __syncthreads();
-    run_chain(lds0, A.c2, CB, A.cb_log2, L5, A, slot0, tid, nthr);
+    run_chain(lds, A.c2, CB, A.cb_log2, L5, c, tid, nthr);
     __syncthreads();
     lds_get(lds, CB, cbl, s, v);
   }
@@ -1059,9 +981,8 @@ static void lds_layout(const DslashArgs& A, int prec, int cb_log2, bool hop, siz
                        size_t& stage) {
   const size_t CB = (size_t)1 << cb_log2;
   const size_t rb = prec == F64 ? 8 : 4;
-  const size_t nrw = A.nrw < 1 ? 1 : (size_t)A.nrw;
-  chain = (A.c1 != CH_NONE || A.c2 != CH_NONE) ? round_up(nrw * CB * A.g.L5 * kChainStride * rb, 16) : 0;
-  red = A.reduce ? round_up(nrw * CB * A.g.L5 * 8, 16) : 0;
+  chain = (A.c1 != CH_NONE || A.c2 != CH_NONE) ? round_up(CB * A.g.L5 * kChainStride * rb, 16) : 0;
+  red = A.reduce ? round_up(CB * A.g.L5 * 8, 16) : 0;
   stage = (hop && A.stage) ? round_up(stage_nbr_bytes((int)CB) + CB * kStageLinkStride * rb, 16) : 0;
 }
 
@@ -1084,17 +1005,14 @@ hipError_t dslash_launch(DslashArgs A, int prec, bool hop, bool dag, bool pro, i
   const int CB = 1 << cb_log2;
   A.cb_log2 = cb_log2;
   A.nblk = (A.g.Vh + CB - 1) / CB;
-  if (A.nrw < 1) A.nrw = 1;
-  if (A.nrw > A.nslots) A.nrw = A.nslots;
-  if (A.nrw > 1 && (CB * A.g.L5) % 64 != 0) A.nrw = 1;  // one RHS per wavefront
   clamp_traversal(A.g, CB, A.order_bt, A.order_yb);
   size_t chain, red, stage;
   lds_layout(A, prec, cb_log2, hop, chain, red, stage);
   A.lds_chain_bytes = (int)std::max(chain, stage);  // offset of the reduction area
   A.lds_stage_off = 0;
   const size_t smem = std::max(chain, stage) + red;
-  const int threads = CB * A.g.L5 * A.nrw;
-  const long long blocks = (long long)A.nblk * ((A.nslots + A.nrw - 1) / A.nrw);
+  const int threads = CB * A.g.L5;
+  const long long blocks = (long long)A.nblk * A.nslots;
   const int grid = (int)round_up((size_t)blocks, 8);
   if (threads > dslash_max_threads(prec) || blocks <= 0) return hipErrorInvalidValue;
   switch (prec) {

@@ -81,6 +81,8 @@ struct mdwf_ctx {
   mdwf::DevBuf red_out;    // reduced doubles
   mdwf::DevBuf tmp64[3];   // FP64 half-field temporaries (setup, updates, finalize)
   mdwf::DevBuf dws;        // operator workspace of mdwf_dslash
+  mdwf::DevBuf job_cache;  // the block of the last mdwf_solve, reused by the next one
+  bool solve_cache = false;  // set while mdwf_solve begins its job
   double* red_host = nullptr;  // pinned
   size_t red_host_n = 0;
   mdwf::CGState* st_host = nullptr;  // pinned
@@ -109,6 +111,7 @@ struct mdwf_job {
   mdwf::Coef5 coef{};
   void* block = nullptr;
   size_t block_bytes = 0;
+  bool keep_block = false;  // mdwf_solve: on mdwf_job_end the block goes back to the context's cache
   std::vector<char*> fx, fr, fp, fpt, ft, fv, fxh, feh;  // fpt = M_phi p
   std::vector<mdwf::CGState> st;
   std::vector<mdwf_cg_stats> stats;

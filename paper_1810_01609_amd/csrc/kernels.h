@@ -66,7 +66,6 @@ struct DslashArgs {
   double* partials;        // [nslots][ntiles] (16-site tiles) when reduce
   int ntiles;
   int nslots;
-  int nrw;                 // RHS per workgroup (they share the staged links; >= 1)
   int nblk;                // filled by the launcher
   int cb_log2;             // filled by the launcher
   int lds_chain_bytes;     // filled by the launcher: offset of the reduction area

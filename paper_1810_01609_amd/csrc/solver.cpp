@@ -354,12 +354,23 @@ extern "C" mdwf_status mdwf_job_begin(mdwf_ctx* c, const mdwf_gauge* g, const md
   iter_model(geom, j->ps, j->bytes_iter, j->flops_iter);
   const SlotLayout L = slot_layout(geom, j->ps);
   j->block_bytes = L.total * (size_t)nrhs;
-  hipError_t e = hipMalloc(&j->block, j->block_bytes);
+  hipError_t e = hipSuccess;
+  if (c->solve_cache && c->job_cache.p != nullptr && c->job_cache.n >= j->block_bytes) {
+    // mdwf_solve: the previous solve's block (same or larger size)
+    j->block = c->job_cache.p;
+    j->block_bytes = c->job_cache.n;
+    c->job_cache.p = nullptr;
+    c->job_cache.n = 0;
+  } else {
+    if (c->solve_cache) release(c->job_cache);  // too small: give its memory back first
+    e = hipMalloc(&j->block, j->block_bytes);
+  }
   if (e != hipSuccess) {
     j->block = nullptr;
     delete j;
     return hip_err(c, e, "mdwf_job_begin: hipMalloc");
   }
+  j->keep_block = c->solve_cache;
   char* p = static_cast<char*>(j->block);
   for (int r = 0; r < nrhs; ++r) {
     j->fr.push_back(p); p += L.fs;
@@ -753,7 +764,15 @@ extern "C" mdwf_status mdwf_job_end(mdwf_job* j) {
     (void)hipSetDevice(j->ctx->device);
     (void)hipStreamSynchronize(j->ctx->stream);
   }
-  if (j->block != nullptr) (void)hipFree(j->block);
+  if (j->block != nullptr) {
+    mdwf_ctx* c = j->ctx;
+    if (j->keep_block && c != nullptr && c->job_cache.p == nullptr) {
+      c->job_cache.p = j->block;  // kept for the context's next mdwf_solve
+      c->job_cache.n = j->block_bytes;
+    } else {
+      (void)hipFree(j->block);
+    }
+  }
   delete j;
   return MDWF_OK;
 }
@@ -763,7 +782,12 @@ extern "C" mdwf_status mdwf_solve(mdwf_ctx* c, const mdwf_gauge* g, const mdwf_a
                                   mdwf_cg_stats* stats) {
   if (c == nullptr) return MDWF_EINVAL;
   mdwf_job* j = nullptr;
+  // a blocking solve reuses the previous solve's device block (hipMalloc of
+  // tens of GB again for every solve costs time); MDWF_SOLVE_CACHE=0 frees it
+  const char* ev = getenv("MDWF_SOLVE_CACHE");
+  c->solve_cache = !(ev != nullptr && ev[0] == '0');
   mdwf_status st = mdwf_job_begin(c, g, act, opts, nrhs, eta, psi, &j);
+  c->solve_cache = false;
   if (st != MDWF_OK) return st;
   mdwf_status sst = mdwf_job_step(c, &j, 1, INT_MAX);
   int32_t done = 0;

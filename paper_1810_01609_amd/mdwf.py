@@ -104,6 +104,7 @@ _SIGS = {
     "mdwf_query_traversal": (_I, [ctypes.POINTER(Action), _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "mdwf_create": (_I, [_I, _P, ctypes.POINTER(_P)]),
     "mdwf_destroy": (_I, [_P]),
+    "mdwf_trim": (_I, [_P]),
     "mdwf_last_error": (ctypes.c_char_p, [_P]),
     "mdwf_stream": (_P, [_P]),
     "mdwf_gauge_load": (_I, [_P, ctypes.POINTER(_I), _P, _I, ctypes.c_uint32, ctypes.POINTER(_P)]),
@@ -229,6 +230,10 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def trim(self):
+        """Release the device memory the context keeps between calls."""
+        self._check(lib().mdwf_trim(self._h), "mdwf_trim")
 
     def stream(self):
         return lib().mdwf_stream(self._h)

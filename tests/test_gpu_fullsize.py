@@ -99,6 +99,7 @@ def test_solve_oracle_residual_full_size(ctx, name, inner, nrhs, verify):
 
     c, act, oact, U = _gauge(name)
     torch.cuda.empty_cache()  # c4 with 12 RHS needs ~270 GB of the 288
+    ctx.trim()  # and the previous solve's cached state goes too
     g = ctx.gauge_load(c["L"], U, precs=("f64", inner))
     eta = torch.zeros((nrhs,) + act.spinor_shape(), dtype=torch.complex128, device="cuda")
     for r in range(nrhs):
