@@ -275,6 +275,23 @@ MDWF_API mdwf_status mdwf_source_physical(mdwf_ctx *ctx, const mdwf_gauge *g, co
 MDWF_API mdwf_status mdwf_dslash(mdwf_ctx *ctx, const mdwf_gauge *g, const mdwf_action *act, int32_t op, int32_t prec,
                         int32_t nrhs, const void *in, void *out);
 
+/* mdwf_dslash without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same operators, arguments, layouts and results
+ * (bitwise) as mdwf_dslash; every temporary -- the device pointer tables, the
+ * per-RHS coefficients and the five internal half-fields per RHS -- lives in
+ * one fixed scratch array of 256 MiB per GPU that the library holds until
+ * the process ends, so the call performs no hipMalloc, hipFree or other
+ * allocation.  Limits: nrhs <= 16 and
+ * 64 KiB + 5 * nrhs * (one half-field in `prec`, padded to 256 B) <= 256 MiB
+ * (e.g. 16^3 x 32 x L5 = 12 in FP16 with one RHS); beyond them EINVAL with
+ * the sizes in the message.  Calls on one stream are ordered; calls on one
+ * GPU that overlap in time (two streams or contexts) share the array and
+ * race.  No kernel timing is recorded for this call.  Asynchronous on the
+ * context stream. */
+MDWF_API mdwf_status mdwf_dslash_noalloc(mdwf_ctx *ctx, const mdwf_gauge *g, const mdwf_action *act, int32_t op,
+                                         int32_t prec, int32_t nrhs, const void *in, void *out);
+
 /* out_e = H_eo in_o (as MDWF_OP_HOP_EO; the odd parity of out is set to zero)
  * computed the way one rank of a 4D domain-decomposed run computes it (paper,
  * "Current State of the Art": pack the halo, communicate it, apply the

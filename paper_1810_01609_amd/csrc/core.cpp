@@ -558,6 +558,7 @@ mdwf_status mdwf_create(int32_t device, void* stream, mdwf_ctx** out) {
   mdwf_ctx* c = new (std::nothrow) mdwf_ctx();
   if (c == nullptr) return MDWF_ENOMEM;
   c->device = device;
+  scratch_init(device);  // this device's address of the no-allocation scratch
   if (stream != nullptr) {
     c->stream = static_cast<hipStream_t>(stream);
     c->own_stream = false;

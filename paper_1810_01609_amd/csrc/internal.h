@@ -162,5 +162,8 @@ void prof_end(mdwf_ctx* c, int cls, double bytes, hipEvent_t e0);
 // position pos
 void prof_chunk_begin(mdwf_ctx* c, int chunk);
 void prof_chunk_commit(mdwf_ctx* c, const std::vector<double>& active_frac);
+// With `device` current: record this device's address of the scratch array
+// behind mdwf_dslash_noalloc (called once per context creation; idempotent).
+void scratch_init(int device);
 
 }  // namespace mdwf

@@ -1,6 +1,7 @@
 // mdwf_dslash: the operators of the even-odd preconditioned Moebius
 // domain-wall system, each built from the fused stencil kernel.
 #include <cstring>
+#include <mutex>
 
 #include "internal.h"
 
@@ -224,6 +225,113 @@ static mdwf_status dslash_body(mdwf_ctx* c, const mdwf_gauge* g, const Geom& geo
     prof_end(c, MDWF_PROF_OTHER, 0, ev);
   }
   return hip_err(c, e, "mdwf_dslash");
+}
+
+// ---------------------------------------------------------------------------
+// mdwf_dslash without allocation, for callers that cannot allocate: the
+// pointer tables, the coefficients and the five internal half-fields per RHS
+// live in `scratch`, one fixed array per GPU that the library holds for the
+// life of the process.  Host code never names the array's symbol as an
+// address: each device's address comes from hipGetSymbolAddress, taken once
+// per device when a context is created on it.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)256 << 20;  // 256 MiB per GPU
+constexpr size_t kScratchTableBytes = (size_t)64 << 10;
+constexpr int kScratchMaxRhs = 16;
+constexpr int kScratchMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kScratchMaxDevices] = {};
+static hipError_t g_scratch_err[kScratchMaxDevices] = {};
+
+// With `device` current: fetch this device's address of `scratch` (once).
+void mdwf::scratch_init(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= kScratchMaxDevices || g_scratch_ptr[device] != nullptr) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  g_scratch_err[device] = e;
+  if (e == hipSuccess) g_scratch_ptr[device] = p;
+}
+
+static void* scratch_ptr(int device, hipError_t& err) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= kScratchMaxDevices) {
+    err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  err = g_scratch_ptr[device] != nullptr ? hipSuccess : g_scratch_err[device];
+  if (g_scratch_ptr[device] == nullptr && err == hipSuccess) err = hipErrorNotInitialized;
+  return g_scratch_ptr[device];
+}
+
+// The tables travel by value in the kernel arguments and are written into the
+// scratch by one small kernel on the caller's stream (no host-to-device copy).
+struct ScratchTables {
+  const char* ptr[8][kScratchMaxRhs];
+  Coef5 coef[kScratchMaxRhs];
+};
+static_assert(sizeof(ScratchTables) <= 3072, "kernel argument size");
+static_assert(8 * kScratchMaxRhs * sizeof(void*) + kScratchMaxRhs * sizeof(Coef5) <= kScratchTableBytes, "tables");
+
+__global__ __launch_bounds__(256) void k_put_tables(ScratchTables t, char* dst) {
+  const char** tab = reinterpret_cast<const char**>(dst);
+  for (int i = threadIdx.x; i < 8 * kScratchMaxRhs; i += blockDim.x) tab[i] = t.ptr[i / kScratchMaxRhs][i % kScratchMaxRhs];
+  Coef5* cf = reinterpret_cast<Coef5*>(dst + 8 * kScratchMaxRhs * sizeof(void*));
+  for (int i = threadIdx.x; i < kScratchMaxRhs; i += blockDim.x) cf[i] = t.coef[i];
+}
+
+extern "C" mdwf_status mdwf_dslash_noalloc(mdwf_ctx* c, const mdwf_gauge* g, const mdwf_action* act, int32_t op,
+                                           int32_t prec, int32_t nrhs, const void* in, void* out) {
+  if (c == nullptr) return MDWF_EINVAL;
+  mdwf_status st = dslash_check(c, "mdwf_dslash_noalloc", g, act, op, prec, nrhs, in, out);
+  if (st != MDWF_OK) return st;
+  if (nrhs > kScratchMaxRhs)
+    return set_err(c, MDWF_EINVAL, "mdwf_dslash_noalloc: nrhs %d exceeds the maximum of %d", nrhs, kScratchMaxRhs);
+  const Geom geom = make_geom(act);
+  const size_t ub = (size_t)geom.Vh * 2 * geom.L5 * 12 * 16;
+  const size_t fb = round_up(spinor_field_bytes(prec, geom.L5, geom.Vh), 256);
+  const size_t need = kScratchTableBytes + fb * 5 * (size_t)nrhs;
+  if (need > kScratchBytes)
+    return set_err(c, MDWF_EINVAL, "mdwf_dslash_noalloc: needs %zu bytes of scratch, more than the %zu it holds", need,
+                   kScratchBytes);
+  (void)hipSetDevice(c->device);
+  hipError_t e = hipSuccess;
+  char* base = static_cast<char*>(scratch_ptr(c->device, e));
+  if (base == nullptr) return hip_err(c, e, "mdwf_dslash_noalloc: scratch address");
+  ScratchTables t{};
+  const char* ib = static_cast<const char*>(in);
+  const char* ob = static_cast<const char*>(out);
+  char* w = base + kScratchTableBytes;
+  const Coef5 coef = make_coef(act);
+  for (int r = 0; r < nrhs; ++r) {
+    t.ptr[0][r] = ib + ub * r;
+    t.ptr[1][r] = ob + ub * r;
+    for (int k = 0; k < 5; ++k) t.ptr[2 + k][r] = w + fb * (5 * r + k);
+    t.ptr[7][r] = nullptr;
+    t.coef[r] = coef;
+  }
+  launch_k(k_put_tables, dim3(1), dim3(256), 0, c->stream, t, base);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(c, e, "mdwf_dslash_noalloc: table kernel");
+  char* const* tab = reinterpret_cast<char* const*>(base);
+  DslashTables d;
+  d.UIN = tab + 0 * kScratchMaxRhs;
+  d.UOUT = tab + 1 * kScratchMaxRhs;
+  d.IE = tab + 2 * kScratchMaxRhs;
+  d.IO = tab + 3 * kScratchMaxRhs;
+  d.OE = tab + 4 * kScratchMaxRhs;
+  d.OO = tab + 5 * kScratchMaxRhs;
+  d.T = tab + 6 * kScratchMaxRhs;
+  d.NUL = tab + 7 * kScratchMaxRhs;
+  d.coef = reinterpret_cast<const Coef5*>(base + 8 * kScratchMaxRhs * sizeof(void*));
+  // kernel timing would create HIP events: it is left off for this call
+  const int prof = c->prof;
+  c->prof = 0;
+  st = dslash_body(c, g, geom, op, prec, nrhs, d);
+  c->prof = prof;
+  return st;
 }
 
 // The hop H_eo computed the way one rank of a domain-decomposed run computes

@@ -113,6 +113,7 @@ _SIGS = {
     "mdwf_source_point": (_I, [_P, ctypes.POINTER(Action), ctypes.POINTER(_I), _I, _I, _P]),
     "mdwf_source_z2": (_I, [_P, ctypes.POINTER(Action), ctypes.c_uint64, _I, _P]),
     "mdwf_propagator_4d": (_I, [_P, ctypes.POINTER(Action), _I, _P, _P]),
+    "mdwf_dslash_noalloc": (_I, [_P, _P, ctypes.POINTER(Action), _I, _I, _I, _P, _P]),
     "mdwf_source_physical": (_I, [_P, _P, ctypes.POINTER(Action), _I, _I, _P, _P]),
     "mdwf_current_source": (_I, [_P, ctypes.POINTER(Action), _I, _I, _P, _P]),
     "mdwf_dslash": (_I, [_P, _P, ctypes.POINTER(Action), _I, _I, _I, _P, _P]),
@@ -305,6 +306,15 @@ class Context:
         st = lib().mdwf_dslash(self._h, gauge.handle, ctypes.byref(act), int(op), p, int(nrhs),
                                _ptr(inp, nb, "in"), _ptr(out, nb, "out"))
         self._check(st, "mdwf_dslash")
+
+    def dslash_noalloc(self, gauge, act: Action, op: int, prec, inp, out, nrhs: int = 1):
+        """mdwf_dslash_noalloc: the same operator with every temporary in the
+        library's fixed per-GPU scratch (no device allocation)."""
+        p = PREC[prec] if isinstance(prec, str) else int(prec)
+        nb = 16 * _numel(act) * nrhs
+        st = lib().mdwf_dslash_noalloc(self._h, gauge.handle, ctypes.byref(act), int(op), p, int(nrhs),
+                                       _ptr(inp, nb, "in"), _ptr(out, nb, "out"))
+        self._check(st, "mdwf_dslash_noalloc")
 
     def hop_split(self, gauge, act: Action, prec, split_mask: int, inp, out, nrhs: int = 1, timed: bool = False):
         """out_e = H_eo in_o as one rank of a domain-decomposed run computes it
