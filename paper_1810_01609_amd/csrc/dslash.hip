@@ -781,6 +781,26 @@ __device__ __forceinline__ int block_first_site(const DslashArgs& A, int q, int 
   return ((t * g.Lz + z) * g.Ly + yb * rows) * g.Lxh + k * CB;
 }
 
+// (RHS slot, site block) of logical workgroup lb in the launch's RHS order.
+// The XCD remap hands XCD k the logical range [k, k + 1) * gridDim.x / 8, so
+// order 2 keeps one eighth of the site blocks on each XCD and walks its RHS
+// one after another there: one RHS's neighbour planes at a time in that L2.
+__device__ __forceinline__ void block_slot(const DslashArgs& A, int lb, int& slot, int& blk) {
+  if (A.rhs_order == 1) {
+    slot = lb / A.nblk;
+    blk = lb - slot * A.nblk;
+  } else if (A.rhs_order == 2) {
+    const int per = A.nblk >> 3;  // site blocks per XCD
+    const int range = per * A.nslots;
+    const int k = lb / range, j = lb - k * range;
+    slot = j / per;
+    blk = k * per + (j - slot * per);
+  } else {
+    slot = lb % A.nslots;
+    blk = lb / A.nslots;
+  }
+}
+
 // FP64 needs ~180 VGPRs per thread (2 waves per SIMD), the 32-bit
 // arithmetic variants fit 128 (4 waves per SIMD).
 template <int P> constexpr int kMaxThreads = P == F64 ? 512 : 1024;
@@ -809,8 +829,9 @@ __global__ __launch_bounds__(kMaxThreads<P>) __attribute__((amdgpu_waves_per_eu(
   const int s = tid >> A.cb_log2;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   if (lb >= A.nslots * A.nblk) return;
-  const int slot = lb % A.nslots;
-  const int cb0 = block_first_site(A, lb / A.nslots, CB);
+  int slot, blk;
+  block_slot(A, lb, slot, blk);
+  const int cb0 = block_first_site(A, blk, CB);
   if (A.active != nullptr && A.active[(size_t)slot * A.active_stride] == 0) return;
   const int cb = cb0 + cbl;
   const bool valid = cb < A.g.Vh;
@@ -1014,6 +1035,7 @@ hipError_t dslash_launch(DslashArgs A, int prec, bool hop, bool dag, bool pro, i
   const int threads = CB * A.g.L5;
   const long long blocks = (long long)A.nblk * A.nslots;
   const int grid = (int)round_up((size_t)blocks, 8);
+  if (A.rhs_order < 0 || A.rhs_order > 2 || A.nslots == 1 || (A.rhs_order == 2 && A.nblk % 8 != 0)) A.rhs_order = 0;
   if (threads > dslash_max_threads(prec) || blocks <= 0) return hipErrorInvalidValue;
   switch (prec) {
     case F64: return launch_p<F64>(A, hop, dag, pro, threads, smem, grid, st);

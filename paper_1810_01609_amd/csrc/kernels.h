@@ -74,6 +74,11 @@ struct DslashArgs {
   int order_bt;            // > 0: blocked (z, t) plane traversal with Bt time slices per block
   int order_yb;            // with order_bt > 0: the xy-plane is cut into order_yb bands of Ly/order_yb rows
   int nt_store;            // 1: the launch's field stores are streaming (non-temporal)
+  // Order of (RHS, site block) over the workgroups of a multi-RHS launch:
+  // 0 = the RHS of one site block consecutive; 1 = RHS by RHS over the whole
+  // grid; 2 = each XCD's eighth of the site blocks, RHS by RHS inside it
+  // (needs nblk % 8 == 0, else 0).  Set by the launcher.
+  int rhs_order;
   int split_mask;          // bit mu: hops across the mu boundary come from halo buffers (skipped here)
   int c1, c2, aux_mode, reduce;
   double coef_y;

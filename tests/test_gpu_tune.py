@@ -1,7 +1,7 @@
 """The launch autotuner: it searches the sites per workgroup and the
 traversal of the fused stencil per key and keeps the result in its table
 (save / load round trip).  Every candidate it can choose is run on its own
-(MDWF_CB_LOG2, MDWF_BT, MDWF_YB) and checked against the FP64 oracle's
+(MDWF_CB_LOG2, MDWF_BT, MDWF_YB, MDWF_RHS_ORDER) and checked against the FP64 oracle's
 M^+M^ at the precision's bar and against the default launch bitwise (the
 candidates only change which workgroup computes which sites, never the
 per-site arithmetic), and tuned runs equal untuned runs bitwise."""
@@ -26,23 +26,27 @@ def test_every_candidate_matches_oracle(prec, monkeypatch):
     U, act, oact = make_case((32, 16, 2, 8), 4, 0.03, 0.2, 12)
     ctx = M.Context(0)
     g = ctx.gauge_load(act.lattice, U, precs=("f64", prec))
-    x = S.random_spinor(act.lattice, act.L5, 21, nrhs=2)
+    # three RHS: every RHS order (side by side, RHS by RHS, RHS by RHS per XCD
+    # eighth) takes the slots through a different workgroup mapping
+    x = S.random_spinor(act.lattice, act.L5, 21, nrhs=3)
     Me = O.parity_mask(oact, 0)
-    want = [O.normal_op(U, Me * x[r], oact) for r in range(2)]
+    want = [O.normal_op(U, Me * x[r], oact) for r in range(3)]
     ref = None
-    cands = [(lg, bt, yb) for lg in (4, 5, 6, 7) for bt, yb in ((0, 1), (2, 1), (4, 1), (8, 1), (2, 4), (4, 4))]
-    for lg, bt, yb in cands:
+    cands = [(lg, bt, yb, o) for lg in (4, 5, 6, 7) for bt, yb in ((0, 1), (2, 1), (4, 1), (8, 1), (2, 4), (4, 4))
+             for o in (0, 1, 2)]
+    for lg, bt, yb, o in cands:
         monkeypatch.setenv("MDWF_CB_LOG2", str(lg))
         monkeypatch.setenv("MDWF_BT", str(bt))
         monkeypatch.setenv("MDWF_YB", str(yb))
+        monkeypatch.setenv("MDWF_RHS_ORDER", str(o))
         out = empty_like_dev(x.shape)
-        ctx.dslash(g, act, M.OP_NORMAL, prec, to_dev(x), out, nrhs=2)
+        ctx.dslash(g, act, M.OP_NORMAL, prec, to_dev(x), out, nrhs=3)
         got = to_host(out)
-        for r in range(2):
-            check(got[r], want[r], TOL[prec], f"{prec} {1 << lg} sites/workgroup Bt={bt} bands={yb} rhs {r}")
+        for r in range(3):
+            check(got[r], want[r], TOL[prec], f"{prec} {1 << lg} sites/workgroup Bt={bt} bands={yb} order {o} rhs {r}")
         if ref is None:
             ref = got
-        assert np.array_equal(got, ref), (lg, bt, yb)
+        assert np.array_equal(got, ref), (lg, bt, yb, o)
     g.free()
     ctx.close()
 
