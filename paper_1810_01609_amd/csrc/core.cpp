@@ -357,7 +357,7 @@ int streaming_stores(const Geom& g, int prec, int nslots) {
   return nslots * half > 48.0e6 ? 1 : 0;
 }
 
-static std::string tune_key(const Geom& g, int prec, const Prog& p, int nslots, bool cg) {
+static std::string tune_key(const Geom& g, int prec, const Prog& p, int nslots, int cg) {
   char buf[256];
   snprintf(buf, sizeof(buf), "dslash5 p%d h%d d%d pr%d c%d.%d a%d r%d u%d s%d L%dx%dx%dx%d L5=%d n%d gfx950",
            prec, (int)p.hop, (int)p.dag, (int)p.pro, p.c1, p.c2, p.aux, p.reduce, (int)cg,
@@ -437,12 +437,16 @@ static void apply_candidate(DslashArgs& A, int code) {
   if (ord1 != 0) A.rhs_order = ord1 - 1;
 }
 
-static double prog_bytes(const Geom& g, int prec, const Prog& p, int nslots, bool cg) {
+static double prog_bytes(const Geom& g, int prec, const Prog& p, int nslots, int cg) {
   const double ne = (double)g.Vh * g.L5;
   const double sb = spinor_site_bytes(prec);
-  // in + out (+ aux); the fused CG update reads p, r, x and writes r, x instead of out
+  const double xs = spinor_site_bytes(prec == F64 ? F64 : F32) / sb;
+  // in + out (+ aux); the fused CG update reads r and writes r instead of
+  // out (+ reads p, reads and writes x), or adds p and x to a plain launch
   double per = 2.0 + (p.aux != AUX_NONE ? 1.0 : 0.0);
-  if (cg) per += 2.0 + 2.0 * spinor_site_bytes(prec == F64 ? F64 : F32) / sb;
+  if (cg == 1) per += 2.0 + 2.0 * xs;
+  if (cg == 2) per += 1.0;
+  if (cg == 3) per += 1.0 + 2.0 * xs;
   double b = nslots * ne * sb * per;
   if (p.hop) b += 8.0 * g.Vh * 12.0 * link_real_bytes(prec);
   return b;
@@ -474,7 +478,7 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int pre
   A.nt_store = streaming_stores(geom, prec, nslots);
   A.split_mask = pr.split;
   if (fuse != nullptr) {
-    A.cg_update = 1;
+    A.cg_update = fuse->mode;
     A.cg_x = fuse->x;
     A.cg_r = fuse->r;
     A.cg_p = fuse->p;
@@ -485,7 +489,7 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int pre
   candidates(geom, prec, A, pr.hop, cand, dflt);
   if (cand.empty()) return hipErrorInvalidValue;
   int lg = dflt;
-  const std::string key = tune_key(geom, prec, pr, nslots, fuse != nullptr);
+  const std::string key = tune_key(geom, prec, pr, nslots, fuse != nullptr ? fuse->mode : 0);
   // the fused CG update is destructive (x, r in place): never tuned on live data
   if (fuse != nullptr) tunable = false;
   auto it = c->tune.find(key);
@@ -527,7 +531,7 @@ hipError_t run_prog(mdwf_ctx* c, const mdwf_gauge* gf, const Geom& geom, int pre
   prof_begin(c, &ev);
   apply_candidate(A, lg);
   hipError_t e = dslash_launch(A, prec, pr.hop, pr.dag, pr.pro, lg & 0xff, c->stream);
-  prof_end(c, cls, prog_bytes(geom, prec, pr, nslots, fuse != nullptr), ev);
+  prof_end(c, cls, prog_bytes(geom, prec, pr, nslots, fuse != nullptr ? fuse->mode : 0), ev);
   return e;
 }
 

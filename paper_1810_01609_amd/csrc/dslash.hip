@@ -781,6 +781,20 @@ __device__ __forceinline__ int block_first_site(const DslashArgs& A, int q, int 
   return ((t * g.Lz + z) * g.Ly + yb * rows) * g.Lxh + k * CB;
 }
 
+// x += alpha p on one (checkerboard index, slice) of the CG's x and p
+template <int P>
+__device__ __forceinline__ void x_update(const DslashArgs& A, const FieldDesc& f, int slot, int cb, int s,
+                                         typename PrecTraits<P>::Real alpha) {
+  constexpr int PX = P == F64 ? F64 : F32;
+  typename PrecTraits<P>::Real pv[24];
+  typename PrecTraits<PX>::Real xv[24];
+  SpinorIO<P>::load(A.cg_p[slot], f, cb, s, pv);
+  SpinorIO<PX>::load(A.cg_x[slot], f, cb, s, xv);
+#pragma unroll
+  for (int k = 0; k < 24; ++k) xv[k] += alpha * pv[k];
+  SpinorIO<PX>::store(A.cg_x[slot], f, cb, s, xv, A.nt_store);
+}
+
 // (RHS slot, site block) of logical workgroup lb in the launch's RHS order.
 // The XCD remap hands XCD k the logical range [k, k + 1) * gridDim.x / 8, so
 // order 2 keeps one eighth of the site blocks on each XCD and walks its RHS
@@ -902,23 +916,19 @@ __global__ __launch_bounds__(kMaxThreads<P>) __attribute__((amdgpu_waves_per_eu(
   }
 
   if constexpr (CGU) {
-    // x += alpha p, r -= alpha q with q = v; v becomes r for the reduction
-    constexpr int PX = P == F64 ? F64 : F32;
+    // r -= alpha q with q = v (and x += alpha p unless a previous launch of
+    // the iteration did it); v becomes r for the reduction
     if (valid) {
       const R alpha = (R)A.cg_st[slot].alpha;
-      R pv[24], rv[24];
-      typename PrecTraits<PX>::Real xv[24];
-      SpinorIO<P>::load(A.cg_p[slot], f, cb, s, pv);
+      R rv[24];
       SpinorIO<P>::load(A.cg_r[slot], f, cb, s, rv);
-      SpinorIO<PX>::load(A.cg_x[slot], f, cb, s, xv);
 #pragma unroll
       for (int k = 0; k < 24; ++k) {
-        xv[k] += alpha * pv[k];
         rv[k] -= alpha * v[k];
         v[k] = rv[k];
       }
-      SpinorIO<PX>::store(A.cg_x[slot], f, cb, s, xv, A.nt_store);
       SpinorIO<P>::store(A.cg_r[slot], f, cb, s, rv, A.nt_store);
+      if (A.cg_update == 1) x_update<P>(A, f, slot, cb, s, alpha);
     }
   }
 
@@ -954,6 +964,7 @@ __global__ __launch_bounds__(kMaxThreads<P>) __attribute__((amdgpu_waves_per_eu(
     lds_get(lds, CB, cbl, s, v);
   }
   if (valid && !CGU) SpinorIO<P>::store(A.out[slot], f, cb, s, v, A.nt_store);
+  if (!CGU && A.cg_update == 3 && valid) x_update<P>(A, f, slot, cb, s, (R)A.cg_st[slot].alpha);
 }
 
 // ---------------------------------------------------------------------------
@@ -974,8 +985,11 @@ static hipError_t launch_t(const DslashArgs& A, int threads, size_t smem, int gr
 template <int P, bool STAGE>
 static hipError_t launch_s(const DslashArgs& A, bool dag, bool pro, int threads, size_t smem, int grid,
                            hipStream_t st) {
-  if (dag && A.cg_update) return launch_t<P, true, true, false, STAGE, true>(A, threads, smem, grid, st);
-  if (A.cg_update) return hipErrorInvalidValue;  // the CG update is fused into M^+ (B2) only
+  // the CG update is fused into M^+ only: r (and x) into its second launch
+  // (B2), x alone possibly into its first (B1)
+  if (dag && (A.cg_update == 1 || A.cg_update == 2))
+    return launch_t<P, true, true, false, STAGE, true>(A, threads, smem, grid, st);
+  if (A.cg_update != 0 && !(dag && A.cg_update == 3)) return hipErrorInvalidValue;
   if (dag) return launch_t<P, true, true, false, STAGE>(A, threads, smem, grid, st);
   if (pro) return launch_t<P, true, false, true, STAGE>(A, threads, smem, grid, st);
   return launch_t<P, true, false, false, STAGE>(A, threads, smem, grid, st);

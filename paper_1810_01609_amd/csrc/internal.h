@@ -145,6 +145,7 @@ struct CgFuse {
   char* const* r;
   char* const* p;
   const CGState* st;
+  int mode;  // DslashArgs::cg_update
 };
 
 // launches with profiling

@@ -82,9 +82,12 @@ struct DslashArgs {
   int split_mask;          // bit mu: hops across the mu boundary come from halo buffers (skipped here)
   int c1, c2, aux_mode, reduce;
   double coef_y;
-  // CG update fused into the epilogue (cg_update = 1): with q the combined
+  // CG update fused into the epilogue.  cg_update = 1: with q the combined
   // value, x += alpha p, r -= alpha q, and the reduction takes |r|^2; q and
-  // `out` are not written.  x is FP64 for an FP64 kernel, FP32 otherwise.
+  // `out` are not written.  2: the same without x (r -= alpha q only).  3:
+  // `out` is written as usual, and x += alpha p is applied on the launch's
+  // (checkerboard index, slice) pairs of x and p (fields of the other parity).
+  // x is FP64 for an FP64 kernel, FP32 otherwise.
   int cg_update;
   char* const* cg_x;
   char* const* cg_r;

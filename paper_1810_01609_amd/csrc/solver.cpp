@@ -542,6 +542,13 @@ extern "C" mdwf_status mdwf_job_step(mdwf_ctx* c, mdwf_job* const* jobs, int32_t
 
   const int stride = (int)(sizeof(CGState) / sizeof(int));
   const double ne = (double)geom.Vh * geom.L5;
+  // x += alpha p rides in the first M^+ launch (B1), whose hop leaves memory
+  // bandwidth unused, rather than in the second (B2), already bound by its
+  // streams of r and x: single RHS FP16 4 % and 12 fused FP32 RHS 1.4 % faster
+  // per iteration on 32^3 x 64, L5 = 12; the same arithmetic, bitwise the same
+  // solve (MDWF_X_IN_B1=0 keeps it in B2)
+  const char* xe = getenv("MDWF_X_IN_B1");
+  const bool x_in_b1 = !(xe != nullptr && xe[0] == '0');
   // One CG iteration is seven launches whose arguments stay fixed while the
   // batch does not change.  With MDWF_GRAPH=1 (and kernel timing and the
   // autotuner off) they are captured once into a HIP graph and replayed.
@@ -592,11 +599,13 @@ extern "C" mdwf_status mdwf_job_step(mdwf_ctx* c, mdwf_job* const* jobs, int32_t
         e = scalar_cg_alpha(S_d, pd, ntiles, n, c->stream);
         prof_end(c, MDWF_PROF_SCALAR, 0, ev);
       }
-      if (e == hipSuccess)
+      if (e == hipSuccess) {  // w_o = M_phi^T M5^-T H^+_oe v (and x += alpha p)
+        const CgFuse fx{X, nullptr, P, S_d, 3};
         e = run_prog(c, j0->g, geom, ps, prog_B1(), V, nullptr, T, coef_d, n, act, stride, nullptr, 0,
-                     MDWF_PROF_DSLASH_INNER, true);
-      if (e == hipSuccess) {  // q = M^+ M^ p, fused with x += alpha p, r -= alpha q, |r|^2
-        const CgFuse fz{X, R, P, S_d};
+                     MDWF_PROF_DSLASH_INNER, true, x_in_b1 ? &fx : nullptr);
+      }
+      if (e == hipSuccess) {  // q = M^+ M^ p, fused with r -= alpha q, |r|^2 (and x += alpha p)
+        const CgFuse fz{X, R, P, S_d, x_in_b1 ? 2 : 1};
         Prog b2 = prog_B2();
         b2.reduce = 1;
         e = run_prog(c, j0->g, geom, ps, b2, T, V, T, coef_d, n, act, stride, pd, ntiles, MDWF_PROF_DSLASH_INNER,

@@ -244,3 +244,26 @@ def test_many_reliable_updates(ctx):
         assert stats[r]["converged"] == 1
         psi_o, _ = O.solve(U, etas[r], oact, tol=1e-12)
         assert rel(got[r], psi_o) < 1e-8
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32", "f16"])
+def test_x_update_placement_is_bitwise_neutral(ctx, monkeypatch, inner):
+    """The CG's x += alpha p runs in the second M^+ launch (with r -= alpha q)
+    or in the first one (MDWF_X_IN_B1); both apply the same alpha to the same
+    p, so solutions, iteration counts and reliable updates agree bitwise, for
+    three fused RHS of a z2 source stepped through several updates."""
+    from paper_1810_01609_amd import mdwf as M
+
+    U, act, oact, g, *_ = _c1(ctx)
+    eta = np.stack([O.z2_source(oact, 70 + r, rhs=r) for r in range(3)])
+    outs = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("MDWF_X_IN_B1", mode)
+        psi = empty_like_dev(eta.shape)
+        st = ctx.solve(g, act, M.CGOpts.make(tol=1e-10, inner=inner), to_dev(eta), psi, nrhs=3)
+        outs[mode] = (to_host(psi), [(s["iters"], s["reliable_updates"]) for s in st])
+        log(f"[x-update] MDWF_X_IN_B1={mode} {inner}: {outs[mode][1]}")
+    assert outs["0"][1] == outs["1"][1]
+    assert np.array_equal(outs["0"][0], outs["1"][0])
+    psi_o, _ = O.solve(U, eta[2], oact, tol=1e-12)
+    assert rel(outs["1"][0][2], psi_o) < 1e-8
