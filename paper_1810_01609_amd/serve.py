@@ -57,13 +57,13 @@ class Request:
 def split_requests(trace, max_rhs):
     """Split requests with more than `max_rhs` sources into chunks that are
     admitted and batched independently (a 12-source request on the largest
-    volume would otherwise have to hold the whole GPU).  Chunk ids are
-    (request id * 1000 + chunk index); `parent` names the request."""
+    volume would otherwise have to hold the whole GPU).  Every part, a whole
+    request included, gets the id (request id * 1000 + chunk index), so no
+    chunk shares an id with another request; `parent` names the request."""
     out = []
     for r in trace:
-        if r.nsrc <= max_rhs:
-            out.append(r)
-            continue
+        if r.nsrc > 1000 * max_rhs:
+            raise ValueError(f"request {r.id}: more than 1000 chunks")
         for k, off in enumerate(range(0, r.nsrc, max_rhs)):
             out.append(Request(id=r.id * 1000 + k, t_arrival=r.t_arrival, volume=r.volume, L5=r.L5, mq=r.mq,
                                nsrc=min(max_rhs, r.nsrc - off), seed=r.seed, parent=r.id, src_offset=off))

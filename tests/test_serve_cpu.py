@@ -112,7 +112,10 @@ def test_split_and_merge_chunks():
     tr = [Request(7, 0.5, (8, 8, 8, 16), 8, 0.01, 12, seed=3), Request(8, 0.6, (8, 8, 8, 16), 8, 0.01, 2)]
     parts = split_requests(tr, 5)
     assert [(p.id, p.nsrc, p.src_offset, p.parent) for p in parts] == [
-        (7000, 5, 0, 7), (7001, 5, 5, 7), (7002, 2, 10, 7), (8, 2, 0, -1)]
+        (7000, 5, 0, 7), (7001, 5, 5, 7), (7002, 2, 10, 7), (8000, 2, 0, 8)]
+    # no part shares an id with another, whatever the ids of whole and split requests
+    many = split_requests([Request(i, 0.0, (8, 8, 8, 16), 8, 0.01, 1 + 5 * (i % 3)) for i in range(40)], 4)
+    assert len({p.id for p in many}) == len(many)
     sched = simulate(parts, FakeBackend(), 1 << 40)
     merged = {r.id: r for r in merge_chunks(sched.done)}
     assert merged[7].nsrc == 12 and merged[8].nsrc == 2
