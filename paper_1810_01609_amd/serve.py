@@ -287,7 +287,16 @@ class GPUBackend:
             psi = torch.zeros_like(eta)
         for k in range(req.nsrc):
             ctx.source_z2(a, req.seed, req.src_offset + k, eta[k])
-        job = ctx.job_begin(self.gauge[tuple(req.volume)], a, self.opts(), eta, psi, nrhs=req.nsrc)
+        try:
+            job = ctx.job_begin(self.gauge[tuple(req.volume)], a, self.opts(), eta, psi, nrhs=req.nsrc)
+        except self.M.MDWFError as e:
+            # the admitted footprints fit the budget, but torch's caching
+            # allocator may still hold blocks freed by finished requests:
+            # return them to the device and try once more
+            if e.status != self.M.ENOMEM:
+                raise
+            torch.cuda.empty_cache()
+            job = ctx.job_begin(self.gauge[tuple(req.volume)], a, self.opts(), eta, psi, nrhs=req.nsrc)
         job.req = req
         job.psi = psi
         return job
@@ -314,6 +323,13 @@ class GPUBackend:
 
     def end(self, job):
         job.end()
+
+    def idle(self, lane):
+        """The lane has no job left: its context releases the FP64 workspace
+        it keeps between calls (each job's footprint counts it while the job
+        runs, so the budget stays exact across lanes)."""
+        if lane in self.lane_ctx:
+            self.lane_ctx[lane].trim()
 
     def close(self):
         for g in self.gauge.values():
@@ -360,6 +376,8 @@ def serve_gpu(trace, backend: GPUBackend, budget_bytes, iters_per_step=25, max_s
                             solutions[r.id] = backend.solution(lane, h)
                         backend.end(h)
                         sched.retire(r, now(), stats)
+                        if not sched.lane_jobs(lane) and hasattr(backend, "idle"):
+                            backend.idle(lane)
                         with wake:
                             wake.notify_all()
         except Exception as e:  # surface errors from worker threads
