@@ -443,3 +443,4 @@ class Job:
         if self._h:
             lib().mdwf_job_end(self._h)
             self._h = ctypes.c_void_p()
+        self._keep = ()  # the job no longer reads eta or writes psi

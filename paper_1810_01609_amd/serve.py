@@ -323,6 +323,7 @@ class GPUBackend:
 
     def end(self, job):
         job.end()
+        job.psi = None  # the request's tensors go with the job, not with the last reference to it
 
     def idle(self, lane):
         """The lane has no job left: its context releases the FP64 workspace
