@@ -279,8 +279,16 @@ def serve_bench(args):
         return [Request(id=d["id"], t_arrival=d["t_arrival"], volume=d["volume"], L5=d["L5"], mq=d["mq"],
                         nsrc=d["nsrc"], seed=100000 + d["id"]) for d in trace]
 
+    import torch
+
     def report(kind):
-        return lambda k, n, t: progress(f"{kind}: {k}/{n} done after {t:.0f} s")
+        def f(k, n, t, used=None):
+            free, total = torch.cuda.mem_get_info()
+            adm = "" if used is None else f", admitted {used / 1e9:.0f} GB"
+            progress(f"{kind}: {k}/{n} done after {t:.0f} s{adm}; device free {free / 1e9:.0f} of "
+                     f"{total / 1e9:.0f} GB, torch allocated {torch.cuda.memory_allocated() / 1e9:.0f} GB, "
+                     f"reserved {torch.cuda.memory_reserved() / 1e9:.0f} GB")
+        return f
 
     inner = args.inner or "f16"
     seeds = {v: 11 + i for i, v in enumerate(vols)}

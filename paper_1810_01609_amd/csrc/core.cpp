@@ -27,6 +27,10 @@ mdwf_status set_err(mdwf_ctx* c, mdwf_status s, const char* fmt, ...) {
 
 mdwf_status hip_err(mdwf_ctx* c, hipError_t e, const char* what) {
   if (e == hipSuccess) return MDWF_OK;
+  // a failed runtime call (a hipMalloc out of memory, say) also leaves the
+  // thread's last-error state set; clear it, or the next launch's
+  // hipGetLastError check would report this error again
+  (void)hipGetLastError();
   if (e == hipErrorOutOfMemory) return set_err(c, MDWF_ENOMEM, "%s: %s", what, hipGetErrorString(e));
   return set_err(c, MDWF_EHIP, "%s: %s", what, hipGetErrorString(e));
 }

@@ -279,6 +279,11 @@ class GPUBackend:
 
         ctx = self.ctx_for(req.lane)
         a = self.act(req)
+        # torch caches freed blocks per stream, and with one stream per lane
+        # its cache can grow to most of the device: when the device's free
+        # memory would not hold this request, the cache goes back first
+        if torch.cuda.mem_get_info(self.device)[0] < self.footprint(req) + 8e9:
+            torch.cuda.empty_cache()
         # the request's tensors are allocated and cleared on the lane's own
         # stream, so the library's kernels that follow on that stream are
         # ordered after the clearing without waiting for any other lane
@@ -341,10 +346,10 @@ class GPUBackend:
 
 
 def serve_gpu(trace, backend: GPUBackend, budget_bytes, iters_per_step=25, max_slots_per_lane=24,
-              keep_solutions=False, progress=None):
+              keep_solutions=False, progress=None, progress_every=10.0):
     """Serve a trace in real time: arrivals at their t_arrival (seconds from
-    start), one worker thread per lane.  progress(done, total, seconds) is
-    called about every 10 s."""
+    start), one worker thread per lane.  progress(done, total, seconds,
+    admitted bytes) is called about every `progress_every` seconds."""
     sched = Scheduler(budget_bytes, backend.footprint, max_slots_per_lane)
     pending = deque(sorted(trace, key=lambda r: r.t_arrival))
     handles = {}
@@ -388,9 +393,9 @@ def serve_gpu(trace, backend: GPUBackend, budget_bytes, iters_per_step=25, max_s
     n_total = len(pending)
     t_report = 0.0
     while len(sched.done) < n_total and not stop.is_set():
-        if progress is not None and now() - t_report >= 10.0:
+        if progress is not None and now() - t_report >= progress_every:
             t_report = now()
-            progress(len(sched.done), n_total, t_report)
+            progress(len(sched.done), n_total, t_report, sched.used)
         while pending and pending[0].t_arrival <= now():
             sched.arrive(pending.popleft())
         for r in sched.admit(now()):
