@@ -395,6 +395,8 @@ def main():
     ap.add_argument("--workload", default="c4")
     ap.add_argument("--inner", default=None, help="inner precision (default: f32 for c1/c2, f16 for c3/c4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sequential", action="store_true",
+                    help="solve the workload's right-hand sides one after another instead of fused (c4)")
     ap.add_argument("--skip-f64", action="store_true", help="skip the plain FP64 reference solve (profiling runs)")
     ap.add_argument("--requests", type=int, default=200, help="c5: requests in the trace")
     ap.add_argument("--fifo-baseline", action="store_true",
@@ -502,6 +504,11 @@ def main():
 
     def step(o, n=nrhs):
         sources(n)
+        if args.sequential:  # the same RHS solved one after another
+            st = []
+            for r in range(n):
+                st.extend(ctx.solve(g, act, o, eta[r:r + 1], psi[r:r + 1], nrhs=1))
+            return st
         return ctx.solve(g, act, o, eta[:n], psi[:n], nrhs=n)
 
     # plain FP64 CG, one RHS at a time, on the first source (reference rate and
@@ -573,6 +580,7 @@ def main():
                          f"{args.inner} inner + f64 reliable updates"),
             "lattice": list(L), "L5": L5, "nrhs": nrhs, "inner": args.inner, "tol": 1e-10, "delta": opts.delta,
             "storage": args.inner, "arithmetic": "f64" if args.inner == "f64" else "f32",
+            "fused": not args.sequential,
         },
         "roofline": {
             "bound": "hbm",
