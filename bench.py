@@ -418,7 +418,8 @@ def main():
     ap.add_argument("--delta", type=float, default=None,
                     help="reliable-update threshold: an update when |r| falls below delta x its maximum since the "
                          "last (default by inner precision: 3e-4 for f32, 0.3 for bf16, 0.1 for f16 and i16)")
-    ap.add_argument("--check-every", type=int, default=8, help="CG iterations between host polls of the solver state")
+    ap.add_argument("--check-every", type=int, default=0,
+                    help="CG iterations between host polls of the solver state (0: the library's size rule)")
     ap.add_argument("--fh", action="store_true", help="Feynman-Hellmann propagator pairs instead of single solves")
     ap.add_argument("--physical", action="store_true",
                     help="--fh: physical 4D propagators (sources (1 - c5 D_W) inject(xi), opposite walls)")

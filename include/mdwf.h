@@ -123,7 +123,7 @@ typedef struct {
   int32_t max_iter;
   int32_t inner;
   int32_t use_initial_guess; /* 1: psi holds the starting guess on entry */
-  int32_t check_every;       /* <= 0: library default                     */
+  int32_t check_every;       /* <= 0: by size (8; 2 for iterations of >= 8 GB) */
 } mdwf_cg_opts;
 
 /* Per right-hand-side result. */
