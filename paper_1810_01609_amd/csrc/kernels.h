@@ -77,7 +77,7 @@ struct DslashArgs {
   // Order of (RHS, site block) over the workgroups of a multi-RHS launch:
   // 0 = the RHS of one site block consecutive; 1 = RHS by RHS over the whole
   // grid; 2 = each XCD's eighth of the site blocks, RHS by RHS inside it
-  // (needs nblk % 8 == 0, else 0).  Set by the launcher.
+  // (needs nblk % 8 == 0; the launcher falls back to 0 otherwise).
   int rhs_order;
   int split_mask;          // bit mu: hops across the mu boundary come from halo buffers (skipped here)
   int c1, c2, aux_mode, reduce;
