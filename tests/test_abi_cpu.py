@@ -79,3 +79,21 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(M, "LIB_PATH", "/nonexistent/libmdwf.so")
     with pytest.raises(M.MDWFError):
         M.lib()
+
+
+def test_ended_job_drops_its_tensor_references():
+    """Job keeps the source and solution tensors alive only while the job
+    runs: end() drops them even if the Job object itself stays referenced
+    (here a job whose handle was already released, so no device call is made)."""
+    import weakref
+
+    class Buf:  # stands in for a tensor
+        pass
+
+    eta, psi = Buf(), Buf()
+    refs = [weakref.ref(eta), weakref.ref(psi)]
+    job = M.Job(None, ctypes.c_void_p(), 2, keep=(eta, psi))
+    del eta, psi
+    assert all(r() is not None for r in refs)
+    job.end()
+    assert all(r() is None for r in refs)
