@@ -120,3 +120,38 @@ def test_split_and_merge_chunks():
     merged = {r.id: r for r in merge_chunks(sched.done)}
     assert merged[7].nsrc == 12 and merged[8].nsrc == 2
     assert merged[7].t_done == max(r.t_done for r in sched.done if r.parent == 7)
+
+
+def test_real_time_loop_frees_idle_lanes_and_keeps_budget():
+    """serve_gpu, the threaded real-time loop, on a host-only backend: every
+    request of a mixed trace completes, the admitted bytes never exceed the
+    budget, every part of a split request keeps its own handle (no job is
+    stepped twice in one call), and a lane whose last job ends is told to
+    release its workspace."""
+    import threading
+
+    from paper_1810_01609_amd.serve import serve_gpu
+
+    class ThreadedFake(FakeBackend):
+        def __init__(self):
+            super().__init__(iters=30)
+            self.idled = []
+            self.lock = threading.Lock()
+
+        def step(self, lane, jobs, iters):
+            assert len({id(j) for j in jobs}) == len(jobs), "a job listed twice in one step"
+            super().step(lane, jobs, iters)
+            return 0.0
+
+        def idle(self, lane):
+            with self.lock:
+                self.idled.append(lane)
+
+    tr = split_requests(_trace(n=24, rate=200.0), 4)
+    be = ThreadedFake()
+    budget = 200 * 10 ** 9
+    sched, _, wall = serve_gpu(tr, be, budget, iters_per_step=10, max_slots_per_lane=16)
+    assert len(sched.done) == len(tr)
+    assert sched.peak_used <= budget and sched.used == 0
+    assert set(be.idled) == {r.lane for r in tr}
+    assert len(merge_chunks(sched.done)) == 24
