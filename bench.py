@@ -414,7 +414,7 @@ def main():
                     help="dslash-only: the normal operator's four launches, or the plain 4D hop")
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--tune", action="store_true", help="enable the launch autotuner")
-    ap.add_argument("--tune-save", default=None, help="dslash-only: write the tuned launch table here")
+    ap.add_argument("--tune-save", default=None, help="write the tuned launch table here")
     ap.add_argument("--delta", type=float, default=None,
                     help="reliable-update threshold: an update when |r| falls below delta x its maximum since the "
                          "last (default by inner precision: 3e-4 for f32, 0.3 for bf16, 0.1 for f16 and i16)")
@@ -480,6 +480,7 @@ def main():
     U = S.gauge_field(L, cfg["eps"], cfg["seed"])
     progress(f"gauge field generated ({time.perf_counter() - t_start:.1f} s)")
     ctx = M.Context(0)
+    ctx.tune_mode(1 if args.tune else 0)  # tuning happens in the warm-up steps
     # achievable bandwidth in this run: the library's STREAM-style copy of 4 GiB
     a = torch.ones(1 << 28, dtype=torch.complex128, device="cuda")
     b = torch.empty_like(a)
@@ -613,6 +614,11 @@ def main():
                          "rel_res_full": st64["rel_res_full"]},
         "kernel_time_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()},
     }
+    if args.tune:
+        line["config"]["tuned"] = True
+        line["tune_entries"] = ctx.tune_entries()
+        if args.tune_save:
+            ctx.tune_save(args.tune_save)
     if not args.no_cpu_baseline and not args.skip_f64:
         progress("timing the CPU oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(cfg, st64["iters"])
