@@ -407,7 +407,8 @@ def main():
     ap.add_argument("--max-rhs", type=int, default=4, help="c5: largest chunk of sources admitted at once")
     ap.add_argument("--max-slots", type=int, default=16, help="c5: largest fused batch per lane")
     ap.add_argument("--iters-per-step", type=int, default=25, help="c5: iterations between batch changes")
-    ap.add_argument("--hbm-budget-gb", type=float, default=240.0, help="c5: device memory for jobs")
+    ap.add_argument("--hbm-budget-gb", type=float, default=float(os.environ.get("MDWF_HBM_BUDGET_GB", 240.0)),
+                    help="c5: device memory for jobs (default: MDWF_HBM_BUDGET_GB, else 240)")
     ap.add_argument("--dslash-only", action="store_true", help="stencil throughput of M^+M^ per precision")
     ap.add_argument("--precs", default="f64,f32,f16,bf16")
     ap.add_argument("--op", default="normal", choices=("normal", "hop"),
